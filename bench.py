@@ -1,0 +1,242 @@
+#!/usr/bin/env python3
+"""Throughput of the sFFT4.0 hot path on one MI355X.
+
+Workload (default): a batch of 512 synthetic signals of length N = 2^22,
+each exactly K = 1000 sparse (support uniform without replacement, magnitude
+1, uniform phase; Sec. 4.1 setup), complex64 in HBM.  One plan for the batch:
+B = 2048 buckets, w = 45057 taps, 12 iterations, (l, q) = (16, 1),
+delta = 1e-6, plan seed 602; signal i uses seed 601 + i.
+
+A step is one pass of the whole hot path over the batch: the fold stage
+(permuted gather + window + fold for every round of every iteration), the
+bucket DFTs, and the recovery stage (subtraction, detection, location,
+estimation, accumulation, top-K).  The timed steps launch the three stages
+one by one with HIP events between them (the per-stage times come from
+those events); the graph replay that sfft_execute_batch uses is timed
+separately as graph_ms_per_step.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "signals/s and HBM GB/s (gather-fold), N=2^22 K=1000, vs dense FFT, rel-L2≤1e-4"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_batch(torch, n, N, K, snr, dtype, dev, seed0):
+    """Planted K-sparse spectra from the seeded generator; time signals by an
+    inverse DFT on the device (input synthesis only), stored in `dtype`."""
+    from paper_2011_05698_amd.signals import planted_spectrum
+
+    if dtype == "f16x2":
+        X = torch.empty((n, N, 2), dtype=torch.float16, device=dev)
+    else:
+        X = torch.empty((n, N), dtype=torch.complex64 if dtype == "c64" else torch.complex128, device=dev)
+    scales = []
+    gen = torch.Generator(device=dev)
+    for i in range(n):
+        sup, vals = planted_spectrum(N, K, seed0 + i)
+        xh = torch.zeros(N, dtype=torch.complex128, device=dev)
+        xh[torch.from_numpy(sup).to(dev)] = torch.from_numpy(vals).to(dev)
+        x = torch.fft.ifft(xh) * N
+        if snr is not None:
+            gen.manual_seed(seed0 + i + 0x5EED)
+            s2 = float((x.abs() ** 2).sum()) / N * 10.0 ** (-snr / 10.0)
+            noise = torch.randn(N, dtype=torch.complex128, device=dev, generator=gen)  # unit variance
+            x = x + noise * math.sqrt(s2)
+        if dtype == "f16x2":
+            s = float(torch.maximum(x.real.abs().max(), x.imag.abs().max()))
+            X[i, :, 0] = (x.real / s).to(torch.float16)
+            X[i, :, 1] = (x.imag / s).to(torch.float16)
+            scales.append(s)
+        else:
+            X[i] = x.to(X.dtype)
+            scales.append(1.0)
+    return X, scales
+
+
+def host_copy(torch, X, i, dtype, scale):
+    import numpy as np
+
+    if dtype == "f16x2":
+        h = X[i].float().cpu().numpy().astype(np.float64)
+        return (h[:, 0] + 1j * h[:, 1]) * scale
+    return X[i].cpu().numpy().astype(np.complex128)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--batch", type=int, default=512)
+    ap.add_argument("--N", type=int, default=2 ** 22)
+    ap.add_argument("--K", type=int, default=1000)
+    ap.add_argument("--B", type=int, default=2048)
+    ap.add_argument("--loops", type=int, default=12)
+    ap.add_argument("--snr", type=float, default=None, help="SNR in dB (default: noiseless)")
+    ap.add_argument("--dtype", default="c64", choices=["c64", "f16x2", "c128"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-dense", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the sparse FFT hot path is built and measured on a single "
+              "MI355X (signals of a batch are independent; see the sharding notes in DESIGN.md).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2011_05698_amd import sfft
+
+    dev = torch.device("cuda:0")
+    N, K, B, M, n = args.N, args.K, args.B, args.loops, args.batch
+    logN = int(math.log2(N))
+    w = (B * logN) | 1
+    l, q, delta, plan_seed, sig_seed = 16, 1.0, 1e-6, 602, 601
+    dt = args.dtype
+
+    log(f"generating {n} signals N=2^{logN} K={K} dtype={dt} snr={args.snr}")
+    t0 = time.perf_counter()
+    X, scales = make_batch(torch, n, N, K, args.snr, dt, dev, sig_seed)
+    torch.cuda.synchronize()
+    log(f"signals ready in {time.perf_counter() - t0:.1f}s")
+
+    t0 = time.perf_counter()
+    plan = sfft.Plan(N, K, B, w, M, l, q, delta=delta, seed=plan_seed, dtype=dt)
+    batch = sfft.Batch([plan] * n)
+    log(f"plan + batch built in {time.perf_counter() - t0:.1f}s (samples/signal {plan.samples})")
+    outs = batch.outputs(dev)
+    xs = [X[i] for i in range(n)]
+    stream = torch.cuda.current_stream()
+
+    batch.execute(xs, scales=scales, outs=outs)      # binds buffers, builds the graph
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        batch.execute(xs, scales=scales, outs=outs)
+    torch.cuda.synchronize()
+    log(f"warmup done ({args.warmup} steps)")
+
+    # ---- timed region: K steps, stage by stage, events between stages ----
+    K_steps = args.steps
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(K_steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(K_steps):
+        ev[k][0].record(stream)
+        batch.launch_stage(0)
+        ev[k][1].record(stream)
+        batch.launch_stage(1)
+        ev[k][2].record(stream)
+        batch.launch_stage(2)
+        ev[k][3].record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stage_ms = [float(np.mean([ev[k][s].elapsed_time(ev[k][s + 1]) for k in range(K_steps)])) for s in range(3)]
+    ms_per_step = elapsed * 1e3 / K_steps
+    value = n * K_steps / elapsed
+    log(f"timed {K_steps} steps: {ms_per_step:.3f} ms/step, {value:.1f} signals/s; stages ms {stage_ms}")
+
+    # graph replay of the same work (the sfft_execute_batch path)
+    torch.cuda.synchronize()
+    tg = time.perf_counter()
+    for _ in range(K_steps):
+        batch.execute(xs, scales=scales, outs=outs)
+    torch.cuda.synchronize()
+    graph_ms = (time.perf_counter() - tg) * 1e3 / K_steps
+
+    # ---- roofline of the dominant kernel (the fold) ----
+    bytes_per_sample = {"c64": 8, "f16x2": 4, "c128": 16}[dt]
+    out_bytes = 16 if dt == "c128" else 8
+    alg_bytes = n * (plan.samples * bytes_per_sample + plan.yhat_elems * out_bytes)
+    achieved = alg_bytes / (stage_ms[0] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                "kernel": "fold_kernel", "alg_bytes_per_launch": alg_bytes,
+                "avg_launch_ms": round(stage_ms[0], 5)}
+
+    # ---- dense FFT of the same N on the same device (context) ----
+    dense = None
+    if not args.no_dense:
+        chunk = min(n, 64)
+        Xd = X[:chunk] if dt != "f16x2" else torch.view_as_complex(X[:chunk].float())
+        Xd = Xd.to(torch.complex64)
+        for _ in range(2):
+            torch.fft.fft(Xd, dim=-1)
+        torch.cuda.synchronize()
+        td = time.perf_counter()
+        reps = 5
+        for _ in range(reps):
+            torch.fft.fft(Xd, dim=-1)
+        torch.cuda.synchronize()
+        dense_s = (time.perf_counter() - td) / (reps * chunk)
+        dense = {"impl": "torch.fft.fft (rocFFT), complex64", "signals_per_s": round(1.0 / dense_s, 1),
+                 "speedup_of_sfft": round(value * dense_s, 3)}
+        del Xd
+        log(f"dense FFT: {1.0 / dense_s:.1f} signals/s")
+
+    # ---- oracle on a bounded sample; parity of that sample ----
+    cpu = None
+    parity = None
+    if not args.no_cpu_baseline:
+        from fractions import Fraction
+
+        from oracle import sfft_oracle as O
+
+        P = O.make_plan(N, K, B, w, M, l, Fraction(q), delta, seed=plan_seed)
+        idxs, vals, counts = outs
+        cnt = counts.cpu().numpy()
+        spent, done, same, worst = 0.0, 0, 0, 0.0
+        while done < n and (spent < args.cpu_seconds or done == 0):
+            xh = host_copy(torch, X, done, dt, scales[done])
+            t1 = time.perf_counter()
+            oi, ov, _ = O.sfft(xh, P)
+            spent += time.perf_counter() - t1
+            c = int(cnt[done])
+            gi = idxs[done][:c].cpu().numpy()
+            gv = vals[done][:c].cpu().numpy().astype(np.complex128)
+            if np.array_equal(gi, oi):
+                same += 1
+                worst = max(worst, float(np.linalg.norm(gv - ov) / max(np.linalg.norm(ov), 1e-300)))
+            done += 1
+        cpu = {"value": round(done / spent, 4), "unit": "signals/s", "cores": 1, "kind": "oracle",
+               "sample": f"first {done} signals of the batch (same inputs), FP64 NumPy oracle, plan untimed"}
+        parity = {"signals_checked": done, "support_identical": same, "max_rel_l2_identical": worst}
+        log(f"oracle: {done} signals in {spent:.1f}s; parity {same}/{done}, max rel-L2 {worst:.2e}")
+
+    line = {
+        "metric": METRIC, "value": round(value, 2), "unit": "signals/s", "n_gpus": 1, "steps": K_steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": {"c64": "f32", "f16x2": "f32", "c128": "f64"}[dt], "data": "synthetic",
+        "config": {"workload": f"sFFT4.0 batch of {n} signals, N=2^{logN}, K={K}, B={B}, w={w}, loops={M}, "
+                               f"l={l}, q={q}, delta={delta}, storage {dt}, "
+                               f"{'noiseless' if args.snr is None else f'SNR {args.snr} dB'}",
+                   "batch": n, "N": N, "K": K, "B": B, "w": w, "loops": M, "multiscale": l, "extension": q,
+                   "storage": dt, "snr_db": args.snr, "samples_per_signal": plan.samples},
+        "roofline": roofline, "cpu_baseline": cpu, "parity": parity, "dense_fft": dense,
+        "stage_ms": {"fold": round(stage_ms[0], 4), "bucket_fft": round(stage_ms[1], 4),
+                     "recover": round(stage_ms[2], 4)},
+        "graph_ms_per_step": round(graph_ms, 4),
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

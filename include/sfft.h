@@ -1,0 +1,220 @@
+/*
+ * sfft.h -- C ABI of the MI355X (gfx950) multiscale sparse FFT hot path.
+ *
+ * The method is sFFT4.0 as analysed in B. Li, Z. Jiang, J. Chen, "On
+ * Performance of Multiscale Sparse Fast Fourier Transform Algorithm"
+ * (arXiv 2011.05698).  Given a length-N signal whose spectrum is (close to)
+ * K-sparse, an execute recovers the K largest coefficients of
+ *     xhat_f = (1/N) sum_j x_j exp(-2 pi i f j / N)        (Sec. 2.1, Eq. 2)
+ * from a sublinear number of samples.
+ *
+ * Conventions that hold for every call:
+ *   - Every call returns sfft_status; nothing throws across the ABI.
+ *   - Pointers named d_* are device (HIP) pointers owned by the caller;
+ *     h_* are host pointers owned by the caller.  The library never frees a
+ *     caller's buffer.  Plans and batches own their device tables and
+ *     workspace and free them in sfft_destroy / sfft_batch_destroy.
+ *   - Execute calls are asynchronous and stream-ordered on `stream` (a
+ *     hipStream_t; NULL is the default stream).  Outputs are valid once the
+ *     stream has been synchronised.  At most one execute may be in flight
+ *     per plan (and per batch): the workspace is per object.
+ *   - Parameter and state errors are reported synchronously, before
+ *     anything is enqueued.  Kernel launch failures return SFFT_ERR_LAUNCH.
+ *     sfft_last_error() returns a thread-local description of the most
+ *     recent failure on the calling thread.
+ *   - Complex values are interleaved (re, im): float2 for SFFT_C64 and
+ *     SFFT_F16X2_SCALED outputs, double2 for SFFT_C128.
+ */
+#ifndef SFFT_H
+#define SFFT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SFFT_OK = 0,
+  SFFT_ERR_PARAM = 1,        /* an argument violates the rules stated at sfft_plan */
+  SFFT_ERR_UNSUPPORTED = 2,  /* valid per the paper, but beyond this library's limits */
+  SFFT_ERR_ALLOC = 3,        /* device or host allocation failed */
+  SFFT_ERR_LAUNCH = 4,       /* a HIP call or kernel launch failed */
+  SFFT_ERR_CAPACITY = 5,     /* recovered-coefficient store overflowed (count reads -1) */
+  SFFT_ERR_STATE = 6         /* object used in a state that does not allow the call */
+} sfft_status;
+
+/* Storage type of the input samples (and, for C128, of all arithmetic). */
+typedef enum {
+  SFFT_C64 = 0,           /* float2 samples; FP32 window, fold, FFT and recovery        */
+  SFFT_C128 = 1,          /* double2 samples; everything in FP64                        */
+  SFFT_F16X2_SCALED = 2   /* __half2 samples x_j ~= scale * (re, im); FP32 arithmetic   */
+} sfft_dtype;
+
+typedef struct sfft_plan_s* sfft_plan_t;
+typedef struct sfft_batch_s* sfft_batch_t;
+
+/* Plan flags. */
+#define SFFT_PLAN_HOST_ONLY 1u   /* build host tables only; no device memory, no execute */
+
+/* Optional plan settings; pass NULL to sfft_plan for the defaults below. */
+typedef struct {
+  double delta;     /* window leakage / truncation level, 0 < delta < 0.1 (default 1e-6)   */
+  uint64_t seed;    /* SplitMix64 seed of the per-iteration sigma, tau0 draws (default 0)  */
+  int32_t dtype;    /* sfft_dtype (default SFFT_C64)                                        */
+  int32_t kahan;    /* 1: compensated (Kahan) summation in the fold (default 0)             */
+  int32_t b_min;    /* smallest bucket count of late iterations, power of two (default 16) */
+  int32_t pad0;
+  double eta;       /* detection floor relative to the strongest bucket (default 1e-4)     */
+  double rho;       /* round-to-round magnitude tolerance of a lone bucket (default 0.25)  */
+  uint32_t flags;   /* SFFT_PLAN_* bits                                                     */
+  uint32_t pad1;
+} sfft_options;
+
+/* Fills *opt with the defaults. */
+void sfft_default_options(sfft_options* opt);
+
+/*
+ * sfft_plan -- validate parameters and build a reusable plan.
+ *
+ * Parameters (the method of Sec. 3; readings of unstated details follow):
+ *   N      signal length, a power of two, 2^4 <= N <= 2^30.
+ *   K      number of coefficients returned, 1 <= K <= B.
+ *   B      buckets of the first iteration, a power of two, 16 <= B <= N/4
+ *          (Sec. 2.3: bucket width L = N/B).  Iteration m uses
+ *          B_m = max(B >> (m-1), b_min) buckets (Sec. 3.3: B halves).
+ *   w      window support of the first iteration, B <= w <= N-1; an even w
+ *          is rounded up to odd.  Iteration m uses w_m = floor(w B_m / B) | 1.
+ *   loops  number of iterations M (Sec. 3.1), 1 <= loops <= 64.
+ *   multiscale  the multiscale parameter l: number of blocks per location
+ *          step (Sec. 3.2), a power of two, 2 <= l <= 1024.
+ *   extension   the extension parameter q (Sec. 3.2): a dyadic rational
+ *          (q * 2^16 an integer), q > 0 and l > q + 1 (regions must shrink).
+ *   opt    NULL for defaults.
+ * Window (Sec. 2.3, Eq. 9-10): width-L boxcar with half-weight edges times a
+ * Gaussian that falls to delta at the support edge; its spectrum Ghat is
+ * tabulated exactly (FP64) out to L/2 + e, e = ceil of the transition
+ * half-width.  The location schedule (Sec. 3.2) and the per-iteration
+ * sigma_m (odd) and tau0_m come from SplitMix64(seed).
+ * Limits (SFFT_ERR_UNSUPPORTED): B <= 8192 for SFFT_C64/SFFT_F16X2_SCALED,
+ * B <= 4096 for SFFT_C128; at most 47 location steps per iteration.
+ * On success *out holds a plan owning its tables and workspace.
+ */
+sfft_status sfft_plan(sfft_plan_t* out, int64_t N, int64_t K, int64_t B, int64_t w, int32_t loops,
+                      int32_t multiscale, double extension, const sfft_options* opt);
+
+/*
+ * sfft_execute -- the whole method on one signal (Sec. 3.1): for every
+ * iteration, HashToBins over its R_m+1 rounds (Lemma 1: permuted gather,
+ * window, fold, B-point DFT with the 1/N factor), subtraction of the
+ * coefficients recovered so far, singleton detection, multiscale location
+ * (Eq. 15-19), verification, median estimation (Eq. 14), dedupe and
+ * accumulation; finally the K largest coefficients.
+ *   d_x     N samples: float2 (C64), double2 (C128) or __half2 (F16X2_SCALED).
+ *   scale   F16X2_SCALED only: the sample value is scale * d_x[j]; ignored otherwise.
+ *   d_idx   K int64: recovered frequencies, ascending.
+ *   d_val   K complex (float2, or double2 for C128): their values.
+ *   d_count 1 int64: number of valid outputs (<= K), or -1 if the
+ *           recovered-coefficient store overflowed (SFFT_ERR_CAPACITY on
+ *           the device side; never happens with the default capacity).
+ * Entries of d_idx/d_val beyond *d_count are left untouched.
+ */
+sfft_status sfft_execute(sfft_plan_t p, const void* d_x, float scale, int64_t* d_idx, void* d_val,
+                         int64_t* d_count, void* stream);
+
+/*
+ * sfft_hash_to_bins -- HashToBins alone (Sec. 2.4, Lemma 1, Eq. 13) for all
+ * iterations and rounds of the plan, without subtraction:
+ *   d_yhat[off_m + j*B_m + i] = (1/N) sum_b y_{m,j}[b] exp(-2 pi i i b / B_m),
+ *   y_{m,j}[b] = sum_{|t| <= h_m, t = b mod B_m} G_t x[sigma_m (t - T_{m,j}) mod N].
+ * off_m is the prefix sum of (R_k+1) B_k over k < m (sfft_iter_info.y_offset);
+ * d_yhat holds sfft_plan_info.yhat_elems complex values (float2, double2 for C128).
+ */
+sfft_status sfft_hash_to_bins(sfft_plan_t p, const void* d_x, float scale, void* d_yhat, void* stream);
+
+/*
+ * sfft_recover -- the reconstruction half of sfft_execute (subtraction,
+ * detection, location, estimation, accumulation, top-K) run on
+ * caller-supplied bucket values in the sfft_hash_to_bins layout.  d_yhat is
+ * read only (the plan copies it into its workspace first).
+ */
+sfft_status sfft_recover(sfft_plan_t p, const void* d_yhat, int64_t* d_idx, void* d_val, int64_t* d_count,
+                         void* stream);
+
+/* Plan-wide facts. */
+typedef struct {
+  int64_t N, K, B, w;
+  int32_t loops, multiscale;
+  double extension, delta;
+  int32_t dtype, kahan;
+  int64_t samples;      /* samples one execute reads: sum_m (R_m+1) w_m (Sec. 2.4 / 3.1 cost) */
+  int64_t yhat_elems;   /* complex elements of the sfft_hash_to_bins output                    */
+  int64_t rec_capacity; /* capacity of the recovered-coefficient store                        */
+  int64_t workspace_bytes; /* device workspace owned by the plan                              */
+  uint64_t seed;
+} sfft_plan_info;
+sfft_status sfft_get_plan_info(sfft_plan_t p, sfft_plan_info* info);
+
+/* Per-iteration facts (m counts from 0).  Arrays are indexed by location
+ * step j = 1..R; index 0 holds the reference round (tau = 0, len = 0). */
+typedef struct {
+  int64_t B, L, w, h, e, R;
+  double d_delta;        /* transition half-width in bins (Ghat falls to delta past L/2 + d_delta) */
+  uint64_t sigma, sigma_inv, tau0;
+  int64_t y_offset;      /* complex-element offset of this iteration in the yhat layout */
+  int64_t T[48], tau[48], len[48];
+  int32_t last_is_enum;  /* always 1: the last step enumerates positions */
+  int32_t pad;
+} sfft_iter_info;
+sfft_status sfft_get_iter_info(sfft_plan_t p, int32_t m, sfft_iter_info* info);
+
+/* Copies iteration m's FP64 window G_0..G_h (h+1 values) and spectrum
+ * Ghat_0..Ghat_{L/2+e} (L/2+e+1 values) into host buffers (either may be NULL). */
+sfft_status sfft_plan_dump_tables(sfft_plan_t p, int32_t m, double* h_window, double* h_ghat);
+
+sfft_status sfft_destroy(sfft_plan_t p);
+
+/*
+ * Batches: many signals, each with its own plan (uneven N, K, B, loops are
+ * allowed), executed together: one launch per kernel stage for the whole
+ * batch, replayed from a HIP graph.  Plans must outlive the batch; a plan
+ * may appear several times.  The batch owns the workspace of its signals.
+ */
+sfft_status sfft_batch_create(sfft_batch_t* out, const sfft_plan_t* h_plans, int32_t n);
+
+/*
+ * sfft_execute_batch -- sfft_execute for every signal s of the batch:
+ *   h_x[s]    device pointer to signal s (dtype of its plan);
+ *   h_scale   per-signal scales (F16X2_SCALED plans) or NULL;
+ *   h_idx[s], h_val[s]  device output buffers of K_s entries;
+ *   d_count   device array of n int64 counts.
+ * The h_* arrays are host arrays of device pointers.  When they differ from
+ * the previous call's, the batch re-uploads its descriptor table with a
+ * blocking copy before enqueueing; repeated calls with the same buffers only
+ * replay the batch's graph on `stream`.
+ */
+sfft_status sfft_execute_batch(sfft_batch_t b, const void* const* h_x, const float* h_scale,
+                               int64_t* const* h_idx, void* const* h_val, int64_t* d_count, void* stream);
+
+/*
+ * sfft_batch_launch_stage -- enqueue one stage of the batch on `stream`, for
+ * timing the stages separately (the sequence fold, bucket DFT, recover is
+ * exactly what sfft_execute_batch replays):
+ *   stage 0: permuted gather + window + fold (HashToBins, Eq. 7, 10, 11)
+ *   stage 1: B-point DFT of every round (Eq. 12 with the 1/N factor)
+ *   stage 2: recovery (subtraction .. top-K)
+ * Uses the buffers bound by the last sfft_execute_batch (SFFT_ERR_STATE if
+ * none).
+ */
+sfft_status sfft_batch_launch_stage(sfft_batch_t b, int32_t stage, void* stream);
+
+sfft_status sfft_batch_destroy(sfft_batch_t b);
+
+const char* sfft_status_string(sfft_status s);
+const char* sfft_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SFFT_H */

@@ -1,0 +1,487 @@
+// C ABI of the library: plan objects, batches, stage sequencing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace sfft;
+
+namespace sfft {
+
+static thread_local std::string g_last_error;
+void set_last_error(const std::string& s) { g_last_error = s; }
+
+// Writes one signal descriptor on the device, in stream order.
+__global__ void set_signal_kernel(SignalDesc* dst, SignalDesc v) { *dst = v; }
+
+}  // namespace sfft
+
+struct sfft_plan_s {
+  HostPlan hp;
+  bool on_device = false;
+  unsigned char* d_mem = nullptr;   // tables, descriptors, work lists, one-signal workspace
+  PlanDesc* d_plan = nullptr;
+  SignalDesc* d_sig = nullptr;
+  FoldTile* d_tiles = nullptr;
+  RoundItem* d_items = nullptr;
+  unsigned char* d_ws = nullptr;
+  uint32_t ntiles = 0, nitems = 0;
+};
+
+struct sfft_batch_s {
+  std::vector<sfft_plan_t> plans;
+  int dtype = 0, kahan = 0;
+  unsigned char* d_mem = nullptr;
+  SignalDesc* d_sigs = nullptr;
+  FoldTile* d_tiles = nullptr;
+  RoundItem* d_items = nullptr;
+  unsigned char* d_ws = nullptr;
+  std::vector<uint64_t> ws_off;
+  uint32_t ntiles = 0, nitems = 0, max_B = 0;
+  std::vector<SignalDesc> bound;    // host copy of the uploaded descriptor table
+  bool has_binding = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t capture_stream = nullptr;
+};
+
+namespace {
+
+sfft_status fail(sfft_status s, const std::string& msg) {
+  set_last_error(msg);
+  return s;
+}
+
+sfft_status hip_fail(hipError_t e, const char* what) {
+  return fail(e == hipErrorOutOfMemory ? SFFT_ERR_ALLOC : SFFT_ERR_LAUNCH,
+              std::string(what) + ": " + hipGetErrorString(e));
+}
+
+uint64_t align256(uint64_t v) { return (v + 255) & ~uint64_t(255); }
+
+void build_work_lists(const HostPlan& hp, uint32_t sig, std::vector<FoldTile>& tiles, std::vector<RoundItem>& items) {
+  for (int m = 0; m < hp.loops; ++m) {
+    const IterDesc& d = hp.iters[m].d;
+    for (uint32_t j = 0; j <= d.R; ++j) {
+      items.push_back(RoundItem{sig, uint16_t(m), uint16_t(j)});
+      for (uint32_t b0 = 0; b0 < d.B; b0 += kFoldTile) tiles.push_back(FoldTile{sig, uint16_t(m), uint16_t(j), b0});
+    }
+  }
+}
+
+// Uploads tables and descriptors of a plan and allocates its one-signal workspace.
+sfft_status upload_plan(sfft_plan_t p) {
+  HostPlan& hp = p->hp;
+  const bool f64 = hp.dtype == SFFT_C128;
+  const uint64_t rs = f64 ? 8 : 4;
+  uint64_t nwin = 0, nghat = 0, ntw = 0;
+  for (auto& it : hp.iters) {
+    nwin += it.G.size();
+    nghat += it.Ghat.size();
+    ntw += it.d.B / 2;
+  }
+  std::vector<FoldTile> tiles;
+  std::vector<RoundItem> items;
+  build_work_lists(hp, 0, tiles, items);
+  p->ntiles = uint32_t(tiles.size());
+  p->nitems = uint32_t(items.size());
+
+  uint64_t off = 0;
+  auto take = [&](uint64_t bytes) {
+    uint64_t o = off;
+    off += align256(bytes);
+    return o;
+  };
+  const uint64_t o_plan = take(sizeof(PlanDesc));
+  const uint64_t o_iters = take(sizeof(IterDesc) * hp.iters.size());
+  const uint64_t o_win = take(nwin * rs);
+  const uint64_t o_ghat = take(nghat * rs);
+  const uint64_t o_tw = take(ntw * 2 * rs);
+  const uint64_t o_sig = take(sizeof(SignalDesc));
+  const uint64_t o_tiles = take(sizeof(FoldTile) * tiles.size());
+  const uint64_t o_items = take(sizeof(RoundItem) * items.size());
+  const uint64_t o_ws = take(hp.desc.ws_bytes);
+
+  hipError_t e = hipMalloc(&p->d_mem, off);
+  if (e != hipSuccess) {
+    p->d_mem = nullptr;
+    return hip_fail(e, "hipMalloc(plan)");
+  }
+  std::vector<unsigned char> host(o_ws, 0);  // everything before the workspace
+  // tables
+  uint64_t wi = 0, gi = 0, ti = 0;
+  for (auto& it : hp.iters) {
+    for (double g : it.G) {
+      if (f64) reinterpret_cast<double*>(host.data() + o_win)[wi++] = g;
+      else reinterpret_cast<float*>(host.data() + o_win)[wi++] = float(g);
+    }
+    for (double g : it.Ghat) {
+      if (f64) reinterpret_cast<double*>(host.data() + o_ghat)[gi++] = g;
+      else reinterpret_cast<float*>(host.data() + o_ghat)[gi++] = float(g);
+    }
+    const uint32_t B = it.d.B;
+    for (uint32_t k = 0; k < B / 2; ++k) {
+      // exp(-2 pi i k / B)
+      const double a = -2.0 * 3.14159265358979323846 * double(k) / double(B);
+      if (f64) {
+        reinterpret_cast<double*>(host.data() + o_tw)[2 * ti] = std::cos(a);
+        reinterpret_cast<double*>(host.data() + o_tw)[2 * ti + 1] = std::sin(a);
+      } else {
+        reinterpret_cast<float*>(host.data() + o_tw)[2 * ti] = float(std::cos(a));
+        reinterpret_cast<float*>(host.data() + o_tw)[2 * ti + 1] = float(std::sin(a));
+      }
+      ++ti;
+    }
+  }
+  for (size_t m = 0; m < hp.iters.size(); ++m)
+    std::memcpy(host.data() + o_iters + m * sizeof(IterDesc), &hp.iters[m].d, sizeof(IterDesc));
+  PlanDesc pd = hp.desc;
+  pd.iters = reinterpret_cast<const IterDesc*>(p->d_mem + o_iters);
+  pd.window = p->d_mem + o_win;
+  pd.ghat = p->d_mem + o_ghat;
+  pd.twiddle = p->d_mem + o_tw;
+  hp.desc = pd;
+  std::memcpy(host.data() + o_plan, &pd, sizeof(PlanDesc));
+  std::memcpy(host.data() + o_tiles, tiles.data(), sizeof(FoldTile) * tiles.size());
+  std::memcpy(host.data() + o_items, items.data(), sizeof(RoundItem) * items.size());
+  e = hipMemcpy(p->d_mem, host.data(), o_ws, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(plan tables)");
+  p->d_plan = reinterpret_cast<PlanDesc*>(p->d_mem + o_plan);
+  p->d_sig = reinterpret_cast<SignalDesc*>(p->d_mem + o_sig);
+  p->d_tiles = reinterpret_cast<FoldTile*>(p->d_mem + o_tiles);
+  p->d_items = reinterpret_cast<RoundItem*>(p->d_mem + o_items);
+  p->d_ws = p->d_mem + o_ws;
+  p->on_device = true;
+  return SFFT_OK;
+}
+
+sfft_status check_plan(sfft_plan_t p) {
+  if (!p) return fail(SFFT_ERR_PARAM, "null plan");
+  if (!p->on_device) return fail(SFFT_ERR_STATE, "plan was built with SFFT_PLAN_HOST_ONLY");
+  return SFFT_OK;
+}
+
+sfft_status enqueue_signal(sfft_plan_t p, const SignalDesc& sd, hipStream_t s) {
+  hipLaunchKernelGGL(set_signal_kernel, dim3(1), dim3(1), 0, s, p->d_sig, sd);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SFFT_OK : hip_fail(e, "set_signal launch");
+}
+
+SignalDesc make_signal(sfft_plan_t p, const void* d_x, float scale, void* y, int64_t* d_idx, void* d_val,
+                       int64_t* d_count) {
+  SignalDesc sd{};
+  sd.plan = p->d_plan;
+  sd.x = d_x;
+  sd.ws = p->d_ws;
+  sd.y = y ? y : p->d_ws + p->hp.desc.off_y;
+  sd.idx = d_idx;
+  sd.val = d_val;
+  sd.count = d_count;
+  sd.scale = scale;
+  return sd;
+}
+
+uint32_t max_B(const HostPlan& hp) {
+  uint32_t b = 0;
+  for (auto& it : hp.iters) b = std::max(b, it.d.B);
+  return b;
+}
+
+sfft_status run_hash(sfft_plan_t p, hipStream_t s) {
+  int e = launch_fold(p->hp.dtype, p->hp.kahan, p->d_sig, p->d_tiles, p->ntiles, s);
+  if (e != hipSuccess) return hip_fail(hipError_t(e), "fold launch");
+  e = launch_bucket_fft(p->hp.dtype, p->d_sig, p->d_items, p->nitems, max_B(p->hp), s);
+  if (e != hipSuccess) return hip_fail(hipError_t(e), "bucket FFT launch");
+  return SFFT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void sfft_default_options(sfft_options* opt) {
+  if (!opt) return;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->delta = 1e-6;
+  opt->seed = 0;
+  opt->dtype = SFFT_C64;
+  opt->kahan = 0;
+  opt->b_min = 16;
+  opt->eta = 1e-4;
+  opt->rho = 0.25;
+  opt->flags = 0;
+}
+
+const char* sfft_status_string(sfft_status s) {
+  switch (s) {
+    case SFFT_OK: return "ok";
+    case SFFT_ERR_PARAM: return "invalid parameter";
+    case SFFT_ERR_UNSUPPORTED: return "unsupported configuration";
+    case SFFT_ERR_ALLOC: return "allocation failed";
+    case SFFT_ERR_LAUNCH: return "launch failed";
+    case SFFT_ERR_CAPACITY: return "capacity exceeded";
+    case SFFT_ERR_STATE: return "invalid state";
+  }
+  return "unknown status";
+}
+
+const char* sfft_last_error(void) { return g_last_error.c_str(); }
+
+sfft_status sfft_plan(sfft_plan_t* out, int64_t N, int64_t K, int64_t B, int64_t w, int32_t loops,
+                      int32_t multiscale, double extension, const sfft_options* opt) {
+  if (!out) return fail(SFFT_ERR_PARAM, "out is NULL");
+  *out = nullptr;
+  sfft_options o;
+  sfft_default_options(&o);
+  if (opt) o = *opt;
+  sfft_plan_t p = new (std::nothrow) sfft_plan_s();
+  if (!p) return fail(SFFT_ERR_ALLOC, "host allocation of the plan failed");
+  std::string err;
+  sfft_status st;
+  try {
+    st = build_host_plan(p->hp, N, K, B, w, loops, multiscale, extension, o, &err);
+  } catch (const std::bad_alloc&) {
+    st = SFFT_ERR_ALLOC;
+    err = "host allocation failed while building the plan";
+  }
+  if (st != SFFT_OK) {
+    delete p;
+    return fail(st, err);
+  }
+  if (!(o.flags & SFFT_PLAN_HOST_ONLY)) {
+    st = upload_plan(p);
+    if (st != SFFT_OK) {
+      if (p->d_mem) (void)hipFree(p->d_mem);
+      delete p;
+      return st;
+    }
+  }
+  *out = p;
+  return SFFT_OK;
+}
+
+sfft_status sfft_destroy(sfft_plan_t p) {
+  if (!p) return SFFT_OK;
+  if (p->d_mem) (void)hipFree(p->d_mem);
+  delete p;
+  return SFFT_OK;
+}
+
+sfft_status sfft_get_plan_info(sfft_plan_t p, sfft_plan_info* info) {
+  if (!p || !info) return fail(SFFT_ERR_PARAM, "null argument");
+  const HostPlan& hp = p->hp;
+  std::memset(info, 0, sizeof(*info));
+  info->N = hp.N; info->K = hp.K; info->B = hp.B; info->w = hp.w;
+  info->loops = hp.loops; info->multiscale = hp.l;
+  info->extension = hp.q; info->delta = hp.delta;
+  info->dtype = hp.dtype; info->kahan = hp.kahan;
+  info->samples = hp.samples;
+  info->yhat_elems = int64_t(hp.desc.y_total);
+  info->rec_capacity = hp.desc.rec_cap;
+  info->workspace_bytes = int64_t(hp.desc.ws_bytes);
+  info->seed = hp.seed;
+  return SFFT_OK;
+}
+
+sfft_status sfft_get_iter_info(sfft_plan_t p, int32_t m, sfft_iter_info* info) {
+  if (!p || !info) return fail(SFFT_ERR_PARAM, "null argument");
+  if (m < 0 || m >= p->hp.loops) return fail(SFFT_ERR_PARAM, "iteration index out of range");
+  const IterHost& it = p->hp.iters[m];
+  std::memset(info, 0, sizeof(*info));
+  info->B = it.d.B; info->L = it.d.L; info->w = it.d.w; info->h = it.d.h; info->e = it.d.e; info->R = it.d.R;
+  info->d_delta = it.d_delta;
+  info->sigma = it.d.sigma; info->sigma_inv = it.d.sigma_inv; info->tau0 = it.d.tau0;
+  info->y_offset = int64_t(it.d.y_off);
+  for (uint32_t j = 0; j <= it.d.R; ++j) {
+    info->T[j] = it.d.T[j];
+    info->tau[j] = it.d.tau[j];
+    info->len[j] = it.d.len[j];
+  }
+  info->last_is_enum = 1;
+  return SFFT_OK;
+}
+
+sfft_status sfft_plan_dump_tables(sfft_plan_t p, int32_t m, double* h_window, double* h_ghat) {
+  if (!p) return fail(SFFT_ERR_PARAM, "null plan");
+  if (m < 0 || m >= p->hp.loops) return fail(SFFT_ERR_PARAM, "iteration index out of range");
+  const IterHost& it = p->hp.iters[m];
+  if (h_window) std::memcpy(h_window, it.G.data(), it.G.size() * sizeof(double));
+  if (h_ghat) std::memcpy(h_ghat, it.Ghat.data(), it.Ghat.size() * sizeof(double));
+  return SFFT_OK;
+}
+
+sfft_status sfft_execute(sfft_plan_t p, const void* d_x, float scale, int64_t* d_idx, void* d_val, int64_t* d_count,
+                         void* stream) {
+  sfft_status st = check_plan(p);
+  if (st != SFFT_OK) return st;
+  if (!d_x || !d_idx || !d_val || !d_count) return fail(SFFT_ERR_PARAM, "null buffer");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  st = enqueue_signal(p, make_signal(p, d_x, scale, nullptr, d_idx, d_val, d_count), s);
+  if (st != SFFT_OK) return st;
+  st = run_hash(p, s);
+  if (st != SFFT_OK) return st;
+  int e = launch_recover(p->hp.dtype, p->d_sig, 1, s);
+  if (e != hipSuccess) return hip_fail(hipError_t(e), "recover launch");
+  return SFFT_OK;
+}
+
+sfft_status sfft_hash_to_bins(sfft_plan_t p, const void* d_x, float scale, void* d_yhat, void* stream) {
+  sfft_status st = check_plan(p);
+  if (st != SFFT_OK) return st;
+  if (!d_x || !d_yhat) return fail(SFFT_ERR_PARAM, "null buffer");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  st = enqueue_signal(p, make_signal(p, d_x, scale, d_yhat, nullptr, nullptr, nullptr), s);
+  if (st != SFFT_OK) return st;
+  return run_hash(p, s);
+}
+
+sfft_status sfft_recover(sfft_plan_t p, const void* d_yhat, int64_t* d_idx, void* d_val, int64_t* d_count,
+                         void* stream) {
+  sfft_status st = check_plan(p);
+  if (st != SFFT_OK) return st;
+  if (!d_yhat || !d_idx || !d_val || !d_count) return fail(SFFT_ERR_PARAM, "null buffer");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const uint64_t bytes = p->hp.desc.y_total * (p->hp.dtype == SFFT_C128 ? 16 : 8);
+  hipError_t e = hipMemcpyAsync(p->d_ws + p->hp.desc.off_y, d_yhat, bytes, hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(yhat)");
+  st = enqueue_signal(p, make_signal(p, nullptr, 1.0f, nullptr, d_idx, d_val, d_count), s);
+  if (st != SFFT_OK) return st;
+  int le = launch_recover(p->hp.dtype, p->d_sig, 1, s);
+  if (le != hipSuccess) return hip_fail(hipError_t(le), "recover launch");
+  return SFFT_OK;
+}
+
+sfft_status sfft_batch_create(sfft_batch_t* out, const sfft_plan_t* h_plans, int32_t n) {
+  if (!out || !h_plans || n < 1) return fail(SFFT_ERR_PARAM, "need at least one plan");
+  *out = nullptr;
+  for (int32_t s = 0; s < n; ++s) {
+    sfft_status st = check_plan(h_plans[s]);
+    if (st != SFFT_OK) return st;
+    if (h_plans[s]->hp.dtype != h_plans[0]->hp.dtype || h_plans[s]->hp.kahan != h_plans[0]->hp.kahan)
+      return fail(SFFT_ERR_PARAM, "all plans of a batch must share dtype and kahan");
+  }
+  sfft_batch_t b = new (std::nothrow) sfft_batch_s();
+  if (!b) return fail(SFFT_ERR_ALLOC, "host allocation of the batch failed");
+  b->plans.assign(h_plans, h_plans + n);
+  b->dtype = h_plans[0]->hp.dtype;
+  b->kahan = h_plans[0]->hp.kahan;
+  std::vector<FoldTile> tiles;
+  std::vector<RoundItem> items;
+  uint64_t ws = 0;
+  for (int32_t s = 0; s < n; ++s) {
+    const HostPlan& hp = h_plans[s]->hp;
+    build_work_lists(hp, uint32_t(s), tiles, items);
+    b->ws_off.push_back(ws);
+    ws += align256(hp.desc.ws_bytes);
+    b->max_B = std::max(b->max_B, max_B(hp));
+  }
+  b->ntiles = uint32_t(tiles.size());
+  b->nitems = uint32_t(items.size());
+  const uint64_t o_sigs = 0;
+  const uint64_t o_tiles = align256(sizeof(SignalDesc) * n);
+  const uint64_t o_items = o_tiles + align256(sizeof(FoldTile) * tiles.size());
+  const uint64_t o_ws = o_items + align256(sizeof(RoundItem) * items.size());
+  hipError_t e = hipMalloc(&b->d_mem, o_ws + ws);
+  if (e != hipSuccess) {
+    delete b;
+    return hip_fail(e, "hipMalloc(batch)");
+  }
+  b->d_sigs = reinterpret_cast<SignalDesc*>(b->d_mem + o_sigs);
+  b->d_tiles = reinterpret_cast<FoldTile*>(b->d_mem + o_tiles);
+  b->d_items = reinterpret_cast<RoundItem*>(b->d_mem + o_items);
+  b->d_ws = b->d_mem + o_ws;
+  e = hipMemcpy(b->d_tiles, tiles.data(), sizeof(FoldTile) * tiles.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(b->d_items, items.data(), sizeof(RoundItem) * items.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    (void)hipFree(b->d_mem);
+    delete b;
+    return hip_fail(e, "batch setup");
+  }
+  *out = b;
+  return SFFT_OK;
+}
+
+sfft_status sfft_execute_batch(sfft_batch_t b, const void* const* h_x, const float* h_scale, int64_t* const* h_idx,
+                               void* const* h_val, int64_t* d_count, void* stream) {
+  if (!b || !h_x || !h_idx || !h_val || !d_count) return fail(SFFT_ERR_PARAM, "null argument");
+  const size_t n = b->plans.size();
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  std::vector<SignalDesc> sig(n);
+  for (size_t i = 0; i < n; ++i) {
+    if (!h_x[i] || !h_idx[i] || !h_val[i]) return fail(SFFT_ERR_PARAM, "null signal buffer");
+    sfft_plan_t p = b->plans[i];
+    SignalDesc& sd = sig[i];
+    sd.plan = p->d_plan;
+    sd.x = h_x[i];
+    sd.ws = b->d_ws + b->ws_off[i];
+    sd.y = b->d_ws + b->ws_off[i] + p->hp.desc.off_y;
+    sd.idx = h_idx[i];
+    sd.val = h_val[i];
+    sd.count = d_count + i;
+    sd.scale = h_scale ? h_scale[i] : 1.0f;
+  }
+  const bool same = b->has_binding && std::memcmp(sig.data(), b->bound.data(), sizeof(SignalDesc) * n) == 0;
+  if (!same) {
+    // new buffers: wait for this batch's work in flight, then upload the table
+    hipError_t e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipMemcpy(b->d_sigs, sig.data(), sizeof(SignalDesc) * n, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "batch descriptor upload");
+    b->bound = sig;
+    b->has_binding = true;
+    if (!b->exec) {
+      hipStream_t cs = b->capture_stream;
+      e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+      int le = launch_fold(b->dtype, b->kahan, b->d_sigs, b->d_tiles, b->ntiles, cs);
+      if (le == hipSuccess) le = launch_bucket_fft(b->dtype, b->d_sigs, b->d_items, b->nitems, b->max_B, cs);
+      if (le == hipSuccess) le = launch_recover(b->dtype, b->d_sigs, uint32_t(n), cs);
+      hipGraph_t g = nullptr;
+      hipError_t ee = hipStreamEndCapture(cs, &g);
+      if (le != hipSuccess) return hip_fail(hipError_t(le), "batch capture launch");
+      if (ee != hipSuccess) return hip_fail(ee, "hipStreamEndCapture");
+      b->graph = g;
+      ee = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+      if (ee != hipSuccess) {
+        b->exec = nullptr;
+        return hip_fail(ee, "hipGraphInstantiate");
+      }
+    }
+  }
+  hipError_t e = hipGraphLaunch(b->exec, s);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return SFFT_OK;
+}
+
+sfft_status sfft_batch_launch_stage(sfft_batch_t b, int32_t stage, void* stream) {
+  if (!b) return fail(SFFT_ERR_PARAM, "null batch");
+  if (!b->has_binding) return fail(SFFT_ERR_STATE, "no buffers bound: call sfft_execute_batch first");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  int e;
+  switch (stage) {
+    case 0: e = launch_fold(b->dtype, b->kahan, b->d_sigs, b->d_tiles, b->ntiles, s); break;
+    case 1: e = launch_bucket_fft(b->dtype, b->d_sigs, b->d_items, b->nitems, b->max_B, s); break;
+    case 2: e = launch_recover(b->dtype, b->d_sigs, uint32_t(b->plans.size()), s); break;
+    default: return fail(SFFT_ERR_PARAM, "stage must be 0, 1 or 2");
+  }
+  if (e != hipSuccess) return hip_fail(hipError_t(e), "stage launch");
+  return SFFT_OK;
+}
+
+sfft_status sfft_batch_destroy(sfft_batch_t b) {
+  if (!b) return SFFT_OK;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+  if (b->d_mem) (void)hipFree(b->d_mem);
+  delete b;
+  return SFFT_OK;
+}
+
+}  // extern "C"

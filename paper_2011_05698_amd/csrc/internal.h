@@ -1,0 +1,125 @@
+// Internal layout shared by the host plan code and the gfx950 kernels.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "sfft.h"
+
+namespace sfft {
+
+constexpr int kMaxRounds = 48;      // R + 1 <= kMaxRounds (reference round + location steps)
+constexpr int kMaxLoops = 64;
+constexpr int kMaxBucketsF32 = 8192;
+constexpr int kMaxBucketsF64 = 4096;
+
+// One iteration of the method, as the kernels read it (plain data, device copy).
+struct IterDesc {
+  uint32_t B, logB, L, logL;
+  uint32_t w, h, e, D;            // D = L/2 + e: reach of a coefficient from a bucket centre
+  uint32_t R;                     // location steps; the iteration has R + 1 rounds
+  uint32_t reach;                 // floor(2D / L): bucket distance of two views of one position
+  uint32_t sigma, sigma_inv;      // odd scaling and its inverse mod N
+  uint32_t tau0, pad0;
+  uint32_t T[kMaxRounds];         // round offsets: T_0 = tau0, T_j = tau0 + tau_j mod N
+  uint32_t tau[kMaxRounds];       // location multipliers (index 0 unused)
+  uint32_t len[kMaxRounds];       // location region lengths (index 0 unused)
+  uint64_t win_off;               // element offset of G_0..G_h in the window table
+  uint64_t ghat_off;              // element offset of Ghat_0..Ghat_D in the spectrum table
+  uint64_t tw_off;                // complex-element offset of B/2 twiddles exp(-2 pi i k / B)
+  uint64_t y_off;                 // complex-element offset of the (R+1) x B bucket block
+  double log_B;                   // ln(B)
+};
+
+// A plan as the kernels read it.
+struct PlanDesc {
+  uint32_t N, logN, K, M;
+  uint32_t l, logl;               // multiscale parameter (power of two)
+  int32_t qn;                     // extension q = qn / 2^logqd
+  uint32_t logqd;
+  uint32_t dtype, kahan;
+  uint32_t rec_cap;               // capacity of the recovered-coefficient store
+  uint32_t Bmax;                  // largest B_m
+  uint32_t pair_cap;              // capacity of the (entry, bucket) list of the subtraction
+  uint32_t sort_cap;              // power of two >= max(rec_cap, Bmax)
+  uint32_t fp64_phase;            // take location phases in FP64 (N >= 2^24)
+  uint32_t pad0;
+  uint64_t y_total;               // complex elements of bucket values per signal
+  uint64_t ws_bytes;              // workspace bytes per signal
+  // byte offsets inside one signal's workspace
+  uint64_t off_y, off_recf0, off_recf1, off_recv0, off_recv1, off_candu, off_candd, off_candv;
+  uint64_t off_pairs, off_cnt, off_start, off_keys, off_p0;
+  double eta, rho;
+  const IterDesc* iters;          // device array of M descriptors
+  const void* window;             // float or double table
+  const void* ghat;               // float or double table
+  const void* twiddle;            // float2 or double2 table
+};
+
+// One signal of a batch (device copy).
+struct SignalDesc {
+  const PlanDesc* plan;
+  const void* x;
+  void* ws;
+  void* y;                         // bucket values (R+1) x B per iteration; normally ws + off_y
+  int64_t* idx;
+  void* val;
+  int64_t* count;
+  float scale;
+  uint32_t pad;
+};
+
+// Work items of the stage kernels.
+struct FoldTile {                  // fold of buckets [b0, b0 + tile) of round j of iteration m
+  uint32_t sig;
+  uint16_t m, j;
+  uint32_t b0;
+};
+struct RoundItem {                 // one (signal, iteration, round)
+  uint32_t sig;
+  uint16_t m, j;
+};
+
+// ------------------------------------------------------------------ host --
+struct IterHost {
+  IterDesc d;
+  double s_t, s_f, d_delta;
+  std::vector<double> G;          // G_0..G_h
+  std::vector<double> Ghat;       // Ghat_0..Ghat_D
+  std::vector<uint8_t> kinds;     // 0 block step, 1 enumeration (index 0 unused)
+};
+
+struct HostPlan {
+  int64_t N, K, B, w;
+  int loops, l;
+  int64_t qn, qd;                 // q = qn / qd, qd a power of two
+  double q, delta, eta, rho;
+  uint64_t seed;
+  int dtype, kahan, b_min;
+  uint32_t flags;
+  std::vector<IterHost> iters;
+  PlanDesc desc;                  // filled with host-side sizes; device pointers set on upload
+  int64_t samples;
+};
+
+// Builds the host part of a plan.  Returns SFFT_OK or an error with *err set.
+sfft_status build_host_plan(HostPlan& hp, int64_t N, int64_t K, int64_t B, int64_t w, int32_t loops,
+                            int32_t l, double q, const sfft_options& opt, std::string* err);
+
+// Workspace layout of one signal (fills the off_* fields of desc).
+void layout_workspace(HostPlan& hp);
+
+void set_last_error(const std::string& s);
+
+// Stage launchers (kernels.hip).  Each returns hipSuccess or the launch error.
+// All signals of one launch share dtype and the Kahan setting.
+constexpr int kFoldTile = 256;      // buckets per fold work item (one thread each)
+int launch_fold(int dtype, int kahan, const SignalDesc* d_sigs, const FoldTile* d_tiles, uint32_t ntiles,
+                void* stream);
+int launch_bucket_fft(int dtype, const SignalDesc* d_sigs, const RoundItem* d_items, uint32_t nitems,
+                      uint32_t max_B, void* stream);
+int launch_recover(int dtype, const SignalDesc* d_sigs, uint32_t nsig, void* stream);
+
+}  // namespace sfft

@@ -1,0 +1,231 @@
+"""HIP path against the FP64 oracle, through the C ABI (needs an MI355X).
+
+Tolerances:
+  * HashToBins: per bucket, the rounding bound of the computation, derived
+    from the arithmetic: a fold of n taps in FP32 and a radix-2 FFT of log2 B
+    stages perturb yhat by at most (n + log2 B + 4) eps (1/N) sum_t |G_t x_t|,
+    eps = 2^-24 (2^-53 for FP64 storage), plus the rounding of the stored
+    window table.
+  * end to end: support bit-exact on noiseless signals; values within
+    relative L2 1e-4 (FP32 and FP16-storage paths) or 1e-10 (FP64 path).
+"""
+
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle.sfft_oracle as O
+from paper_2011_05698_amd.signals import SignalSpec, make_signal
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2011_05698_amd import sfft
+    return sfft
+
+
+DEV = "cuda"
+CDT = {"c64": torch.complex64, "c128": torch.complex128}
+
+
+def to_dev(x, dtype):
+    if dtype == "f16x2":
+        s = float(max(np.max(np.abs(x.real)), np.max(np.abs(x.imag))))
+        h = np.stack([x.real / s, x.imag / s], axis=1).astype(np.float16)
+        xq = (h[:, 0].astype(np.float64) + 1j * h[:, 1].astype(np.float64)) * s
+        return torch.from_numpy(h).to(DEV), s, xq
+    xd = torch.from_numpy(x.astype(np.complex64 if dtype == "c64" else np.complex128)).to(DEV)
+    return xd, 1.0, xd.cpu().numpy().astype(np.complex128)
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def hash_bound(x, it, T, eps, N):
+    """Rounding bound of one round of HashToBins, per bucket (see module doc)."""
+    h = it.h
+    t = np.arange(-h, h + 1)
+    idx = (it.sigma * (t - T)) % N
+    mag = np.abs(it.G[np.abs(t)]) * np.abs(x[idx])
+    ntaps = math.ceil(it.w / it.B)
+    return (ntaps + int(math.log2(it.B)) + 4) * eps * mag.sum() / N
+
+
+CASES_HASH = [
+    # N, K, B, w, loops, l, q, delta, dtype
+    (2 ** 14, 50, 512, 7169, 8, 16, Fraction(1), 1e-8, "c128"),
+    (2 ** 14, 50, 512, 7169, 8, 4, Fraction(1, 4), 1e-8, "c64"),
+    (2 ** 16, 200, 512, 8193, 6, 16, Fraction(1), 1e-6, "c64"),
+    (2 ** 12, 10, 64, 769, 4, 8, Fraction(3, 2), 1e-7, "c64"),
+    (2 ** 16, 200, 512, 8193, 6, 16, Fraction(1), 1e-6, "f16x2"),
+]
+
+
+@pytest.mark.parametrize("case", CASES_HASH, ids=lambda c: f"N{c[0]}_B{c[2]}_{c[8]}")
+def test_hash_to_bins_parity(sf, case):
+    N, K, B, w, M, l, q, delta, dt = case
+    x, _, _ = make_signal(SignalSpec(N, K, 11, snr_db=30))
+    xd, scale, xq = to_dev(x, dt)
+    P = O.make_plan(N, K, B, w, M, l, q, delta, seed=12)
+    plan = sf.Plan(N, K, B, w, M, l, q, delta=delta, seed=12, dtype=dt)
+    y = plan.hash_to_bins(xd, scale).cpu().numpy().astype(np.complex128)
+    torch.cuda.synchronize()
+    eps = 2.0 ** -53 if dt == "c128" else 2.0 ** -24
+    for m, it in enumerate(P.iters):
+        g = plan.iteration(m)
+        for j in range(it.R + 1):
+            want = O.hash_to_bins(xq, it.sigma, it.T[j], it.G, it.B)
+            got = y[g["y_offset"] + j * it.B: g["y_offset"] + (j + 1) * it.B]
+            bound = hash_bound(xq, it, it.T[j], eps, N)
+            err = np.max(np.abs(got - want))
+            assert err <= bound, f"m={m} j={j}: err {err:.3g} > bound {bound:.3g}"
+
+
+E2E = [
+    # N, K, B, w, loops, l, q, delta, dtype, snr, signal seed, plan seed
+    (2 ** 14, 50, 512, 7169, 8, 16, Fraction(1), 1e-8, "c128", None, 101, 102),
+    (2 ** 14, 50, 512, 7169, 8, 4, Fraction(1, 4), 1e-8, "c128", None, 101, 102),
+    (2 ** 14, 50, 512, 7169, 8, 16, Fraction(1), 1e-8, "c64", None, 101, 102),
+    (2 ** 12, 10, 128, 1537, 6, 16, Fraction(1), 1e-8, "c64", None, 7, 8),
+    (2 ** 16, 200, 512, 8193, 10, 16, Fraction(1), 1e-6, "c64", None, 9, 10),
+    (2 ** 18, 300, 1024, 18433, 10, 16, Fraction(1, 2), 1e-6, "c64", None, 21, 22),
+    (2 ** 16, 200, 512, 8193, 10, 16, Fraction(1), 1e-6, "f16x2", None, 9, 10),
+]
+
+
+def run_gpu(sf, plan, xd, scale):
+    idx, val, cnt = plan.execute(xd, scale)
+    torch.cuda.synchronize()
+    c = int(cnt.item())
+    return idx[:c].cpu().numpy(), val[:c].cpu().numpy().astype(np.complex128), c
+
+
+@pytest.mark.parametrize("case", E2E, ids=lambda c: f"N{c[0]}_K{c[1]}_l{c[5]}_q{c[6]}_{c[8]}")
+def test_execute_parity_noiseless(sf, case):
+    N, K, B, w, M, l, q, delta, dt, snr, ss, ps = case
+    x, sup, vals = make_signal(SignalSpec(N, K, ss, snr))
+    xd, scale, xq = to_dev(x, dt)
+    P = O.make_plan(N, K, B, w, M, l, q, delta, seed=ps)
+    oidx, oval, _ = O.sfft(xq, P)
+    plan = sf.Plan(N, K, B, w, M, l, q, delta=delta, seed=ps, dtype=dt)
+    gidx, gval, c = run_gpu(sf, plan, xd, scale)
+    assert np.array_equal(oidx, np.sort(sup)), "oracle must recover the planted support"
+    assert np.array_equal(gidx, oidx), f"support differs: {set(gidx) ^ set(oidx)}"
+    tol = 1e-10 if dt == "c128" else 1e-4
+    assert rel_l2(gval, oval) <= tol, rel_l2(gval, oval)
+
+
+def test_recover_on_oracle_buckets(sf):
+    """Recovery alone: given the oracle's bucket values, the GPU's decisions
+    match the oracle's (same support) and values agree to FP32 rounding."""
+    N, K, B, w, M, l, q, delta = 2 ** 16, 200, 512, 8193, 10, 16, Fraction(1), 1e-6
+    x, sup, _ = make_signal(SignalSpec(N, K, 9))
+    P = O.make_plan(N, K, B, w, M, l, q, delta, seed=10)
+    plan = sf.Plan(N, K, B, w, M, l, q, delta=delta, seed=10, dtype="c64")
+    y = np.concatenate([np.concatenate([O.hash_to_bins(x, it.sigma, it.T[j], it.G, it.B) for j in range(it.R + 1)])
+                        for it in P.iters])
+    idx, val, cnt = plan.recover(torch.from_numpy(y.astype(np.complex64)).to(DEV))
+    torch.cuda.synchronize()
+    c = int(cnt.item())
+    oidx, oval, _ = O.sfft(x, P)
+    assert np.array_equal(idx[:c].cpu().numpy(), oidx)
+    assert rel_l2(val[:c].cpu().numpy().astype(np.complex128), oval) <= 1e-4
+
+
+def test_metric_shape_single_signal(sf):
+    """N = 2^22, K = 1000, B = 2048, w = 45057, 12 iterations, (l, q) = (16, 1):
+    the full-size workload of one signal, element by element."""
+    N, K, B, w, M, l, q, delta = 2 ** 22, 1000, 2048, 45057, 12, 16, Fraction(1), 1e-6
+    x, sup, _ = make_signal(SignalSpec(N, K, 601))
+    xd, scale, xq = to_dev(x, "c64")
+    P = O.make_plan(N, K, B, w, M, l, q, delta, seed=602)
+    oidx, oval, _ = O.sfft(xq, P)
+    plan = sf.Plan(N, K, B, w, M, l, q, delta=delta, seed=602)
+    gidx, gval, c = run_gpu(sf, plan, xd, scale)
+    assert np.array_equal(oidx, np.sort(sup))
+    assert np.array_equal(gidx, oidx)
+    assert rel_l2(gval, oval) <= 1e-4
+
+
+def test_noisy_support_agreement(sf):
+    """20 dB noise (N = 2^20, K = 1000, B = 8192): decisions may flip at near
+    ties; the supports must still agree almost everywhere and the values of
+    the common support within FP32 noise of the oracle."""
+    N, K, B, w, M, l, q, delta = 2 ** 20, 1000, 8192, 163841, 12, 16, Fraction(1, 8), 1e-6
+    x, sup, _ = make_signal(SignalSpec(N, K, 201, 20))
+    xd, scale, xq = to_dev(x, "c64")
+    P = O.make_plan(N, K, B, w, M, l, q, delta, seed=202)
+    oidx, oval, _ = O.sfft(xq, P)
+    plan = sf.Plan(N, K, B, w, M, l, q, delta=delta, seed=202)
+    gidx, gval, c = run_gpu(sf, plan, xd, scale)
+    common = np.intersect1d(gidx, oidx)
+    assert len(common) >= 0.99 * len(oidx), (len(common), len(oidx))
+    gi = {f: v for f, v in zip(gidx, gval)}
+    oi = {f: v for f, v in zip(oidx, oval)}
+    a = np.array([gi[f] for f in common])
+    b = np.array([oi[f] for f in common])
+    assert rel_l2(a, b) <= 1e-3
+
+
+def test_batch_uneven_matches_single(sf):
+    """Signals of different N and K in one batch give exactly what single
+    executes give, and match the oracle."""
+    specs = [(2 ** 14, 40, 512, 7169, 8), (2 ** 16, 120, 256, 4097, 8), (2 ** 12, 8, 64, 769, 6),
+             (2 ** 14, 40, 512, 7169, 8), (2 ** 18, 60, 128, 2305, 8)]
+    plans, xs, singles, oracles = [], [], [], []
+    for s, (N, K, B, w, M) in enumerate(specs):
+        x, _, _ = make_signal(SignalSpec(N, K, 700 + s))
+        xd, scale, xq = to_dev(x, "c64")
+        pl = sf.Plan(N, K, B, w, M, 16, 1.0, delta=1e-6, seed=800 + s)
+        plans.append(pl)
+        xs.append(xd)
+        singles.append(run_gpu(sf, pl, xd, 1.0))
+        oracles.append(O.sfft(xq, O.make_plan(N, K, B, w, M, 16, 1, 1e-6, seed=800 + s))[:2])
+    batch = sf.Batch(plans)
+    for rep in range(2):
+        idxs, vals, counts = batch.execute(xs)
+        torch.cuda.synchronize()
+        for s in range(len(specs)):
+            c = int(counts[s].item())
+            gi = idxs[s][:c].cpu().numpy()
+            gv = vals[s][:c].cpu().numpy()
+            assert np.array_equal(gi, singles[s][0])
+            assert np.array_equal(gv, singles[s][1].astype(np.complex64))
+            assert np.array_equal(gi, oracles[s][0])
+            assert rel_l2(gv.astype(np.complex128), oracles[s][1]) <= 1e-4
+
+
+def test_edge_cases(sf):
+    N, B = 2 ** 12, 64
+    plan = sf.Plan(N, 3, B, (B * 12) | 1, 6, 16, 1.0, delta=1e-8, seed=4)
+    z = torch.zeros(N, dtype=torch.complex64, device=DEV)
+    _, _, c = run_gpu(sf, plan, z, 1.0)
+    assert c == 0
+    n = np.arange(N)
+    x = (0.3 - 0.4j) * np.exp(2j * np.pi * 1234 * n / N)
+    gi, gv, c = run_gpu(sf, plan, torch.from_numpy(x.astype(np.complex64)).to(DEV), 1.0)
+    assert c == 1 and gi[0] == 1234 and abs(gv[0] - (0.3 - 0.4j)) < 1e-5
+    # ties in magnitude: smaller frequencies win
+    x = sum(np.exp(2j * np.pi * f * n / N) for f in (100, 50, 3000, 7))
+    gi, _, c = run_gpu(sf, plan, torch.from_numpy(x.astype(np.complex64)).to(DEV), 1.0)
+    O_idx, _, _ = O.sfft(x.astype(np.complex64).astype(np.complex128),
+                         O.make_plan(N, 3, B, (B * 12) | 1, 6, 16, 1, 1e-8, seed=4))
+    assert c == 3 and np.array_equal(gi, O_idx)
+
+
+def test_deterministic(sf):
+    N, K, B, w, M = 2 ** 16, 200, 512, 8193, 10
+    x, _, _ = make_signal(SignalSpec(N, K, 9, 20))
+    xd, _, _ = to_dev(x, "c64")
+    plan = sf.Plan(N, K, B, w, M, 16, 1.0, delta=1e-6, seed=10)
+    a = run_gpu(sf, plan, xd, 1.0)
+    b = run_gpu(sf, plan, xd, 1.0)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
