@@ -17,9 +17,6 @@ namespace sfft {
 static thread_local std::string g_last_error;
 void set_last_error(const std::string& s) { g_last_error = s; }
 
-// Writes one signal descriptor on the device, in stream order.
-__global__ void set_signal_kernel(SignalDesc* dst, SignalDesc v) { *dst = v; }
-
 }  // namespace sfft
 
 struct sfft_plan_s {
@@ -27,7 +24,6 @@ struct sfft_plan_s {
   bool on_device = false;
   unsigned char* d_mem = nullptr;   // tables, descriptors, work lists, one-signal workspace
   PlanDesc* d_plan = nullptr;
-  SignalDesc* d_sig = nullptr;
   FoldTile* d_tiles = nullptr;
   RoundItem* d_items = nullptr;
   unsigned char* d_ws = nullptr;
@@ -103,7 +99,6 @@ sfft_status upload_plan(sfft_plan_t p) {
   const uint64_t o_win = take(nwin * rs);
   const uint64_t o_ghat = take(nghat * rs);
   const uint64_t o_tw = take(ntw * 2 * rs);
-  const uint64_t o_sig = take(sizeof(SignalDesc));
   const uint64_t o_tiles = take(sizeof(FoldTile) * tiles.size());
   const uint64_t o_items = take(sizeof(RoundItem) * items.size());
   const uint64_t o_ws = take(hp.desc.ws_bytes);
@@ -153,7 +148,6 @@ sfft_status upload_plan(sfft_plan_t p) {
   e = hipMemcpy(p->d_mem, host.data(), o_ws, hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy(plan tables)");
   p->d_plan = reinterpret_cast<PlanDesc*>(p->d_mem + o_plan);
-  p->d_sig = reinterpret_cast<SignalDesc*>(p->d_mem + o_sig);
   p->d_tiles = reinterpret_cast<FoldTile*>(p->d_mem + o_tiles);
   p->d_items = reinterpret_cast<RoundItem*>(p->d_mem + o_items);
   p->d_ws = p->d_mem + o_ws;
@@ -167,10 +161,11 @@ sfft_status check_plan(sfft_plan_t p) {
   return SFFT_OK;
 }
 
-sfft_status enqueue_signal(sfft_plan_t p, const SignalDesc& sd, hipStream_t s) {
-  hipLaunchKernelGGL(set_signal_kernel, dim3(1), dim3(1), 0, s, p->d_sig, sd);
-  hipError_t e = hipGetLastError();
-  return e == hipSuccess ? SFFT_OK : hip_fail(e, "set_signal launch");
+SigArg single(const SignalDesc& sd) {
+  SigArg a;
+  a.table = nullptr;
+  a.one = sd;
+  return a;
 }
 
 SignalDesc make_signal(sfft_plan_t p, const void* d_x, float scale, void* y, int64_t* d_idx, void* d_val,
@@ -193,12 +188,19 @@ uint32_t max_B(const HostPlan& hp) {
   return b;
 }
 
-sfft_status run_hash(sfft_plan_t p, hipStream_t s) {
-  int e = launch_fold(p->hp.dtype, p->hp.kahan, p->d_sig, p->d_tiles, p->ntiles, s);
+sfft_status run_hash(sfft_plan_t p, const SigArg& a, hipStream_t s) {
+  int e = launch_fold(p->hp.dtype, p->hp.kahan, a, p->d_tiles, p->ntiles, s);
   if (e != hipSuccess) return hip_fail(hipError_t(e), "fold launch");
-  e = launch_bucket_fft(p->hp.dtype, p->d_sig, p->d_items, p->nitems, max_B(p->hp), s);
+  e = launch_bucket_fft(p->hp.dtype, a, p->d_items, p->nitems, max_B(p->hp), s);
   if (e != hipSuccess) return hip_fail(hipError_t(e), "bucket FFT launch");
   return SFFT_OK;
+}
+
+SigArg table_arg(const sfft_batch_s* b) {
+  SigArg a;
+  std::memset(&a, 0, sizeof(a));
+  a.table = b->d_sigs;
+  return a;
 }
 
 }  // namespace
@@ -322,11 +324,10 @@ sfft_status sfft_execute(sfft_plan_t p, const void* d_x, float scale, int64_t* d
   if (st != SFFT_OK) return st;
   if (!d_x || !d_idx || !d_val || !d_count) return fail(SFFT_ERR_PARAM, "null buffer");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  st = enqueue_signal(p, make_signal(p, d_x, scale, nullptr, d_idx, d_val, d_count), s);
+  const SigArg a = single(make_signal(p, d_x, scale, nullptr, d_idx, d_val, d_count));
+  st = run_hash(p, a, s);
   if (st != SFFT_OK) return st;
-  st = run_hash(p, s);
-  if (st != SFFT_OK) return st;
-  int e = launch_recover(p->hp.dtype, p->d_sig, 1, s);
+  int e = launch_recover(p->hp.dtype, a, 1, s);
   if (e != hipSuccess) return hip_fail(hipError_t(e), "recover launch");
   return SFFT_OK;
 }
@@ -336,9 +337,7 @@ sfft_status sfft_hash_to_bins(sfft_plan_t p, const void* d_x, float scale, void*
   if (st != SFFT_OK) return st;
   if (!d_x || !d_yhat) return fail(SFFT_ERR_PARAM, "null buffer");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  st = enqueue_signal(p, make_signal(p, d_x, scale, d_yhat, nullptr, nullptr, nullptr), s);
-  if (st != SFFT_OK) return st;
-  return run_hash(p, s);
+  return run_hash(p, single(make_signal(p, d_x, scale, d_yhat, nullptr, nullptr, nullptr)), s);
 }
 
 sfft_status sfft_recover(sfft_plan_t p, const void* d_yhat, int64_t* d_idx, void* d_val, int64_t* d_count,
@@ -350,9 +349,7 @@ sfft_status sfft_recover(sfft_plan_t p, const void* d_yhat, int64_t* d_idx, void
   const uint64_t bytes = p->hp.desc.y_total * (p->hp.dtype == SFFT_C128 ? 16 : 8);
   hipError_t e = hipMemcpyAsync(p->d_ws + p->hp.desc.off_y, d_yhat, bytes, hipMemcpyDeviceToDevice, s);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(yhat)");
-  st = enqueue_signal(p, make_signal(p, nullptr, 1.0f, nullptr, d_idx, d_val, d_count), s);
-  if (st != SFFT_OK) return st;
-  int le = launch_recover(p->hp.dtype, p->d_sig, 1, s);
+  int le = launch_recover(p->hp.dtype, single(make_signal(p, nullptr, 1.0f, nullptr, d_idx, d_val, d_count)), 1, s);
   if (le != hipSuccess) return hip_fail(hipError_t(le), "recover launch");
   return SFFT_OK;
 }
@@ -439,9 +436,10 @@ sfft_status sfft_execute_batch(sfft_batch_t b, const void* const* h_x, const flo
       hipStream_t cs = b->capture_stream;
       e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
       if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-      int le = launch_fold(b->dtype, b->kahan, b->d_sigs, b->d_tiles, b->ntiles, cs);
-      if (le == hipSuccess) le = launch_bucket_fft(b->dtype, b->d_sigs, b->d_items, b->nitems, b->max_B, cs);
-      if (le == hipSuccess) le = launch_recover(b->dtype, b->d_sigs, uint32_t(n), cs);
+      const SigArg a = table_arg(b);
+      int le = launch_fold(b->dtype, b->kahan, a, b->d_tiles, b->ntiles, cs);
+      if (le == hipSuccess) le = launch_bucket_fft(b->dtype, a, b->d_items, b->nitems, b->max_B, cs);
+      if (le == hipSuccess) le = launch_recover(b->dtype, a, uint32_t(n), cs);
       hipGraph_t g = nullptr;
       hipError_t ee = hipStreamEndCapture(cs, &g);
       if (le != hipSuccess) return hip_fail(hipError_t(le), "batch capture launch");
@@ -464,10 +462,11 @@ sfft_status sfft_batch_launch_stage(sfft_batch_t b, int32_t stage, void* stream)
   if (!b->has_binding) return fail(SFFT_ERR_STATE, "no buffers bound: call sfft_execute_batch first");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   int e;
+  const SigArg a = table_arg(b);
   switch (stage) {
-    case 0: e = launch_fold(b->dtype, b->kahan, b->d_sigs, b->d_tiles, b->ntiles, s); break;
-    case 1: e = launch_bucket_fft(b->dtype, b->d_sigs, b->d_items, b->nitems, b->max_B, s); break;
-    case 2: e = launch_recover(b->dtype, b->d_sigs, uint32_t(b->plans.size()), s); break;
+    case 0: e = launch_fold(b->dtype, b->kahan, a, b->d_tiles, b->ntiles, s); break;
+    case 1: e = launch_bucket_fft(b->dtype, a, b->d_items, b->nitems, b->max_B, s); break;
+    case 2: e = launch_recover(b->dtype, a, uint32_t(b->plans.size()), s); break;
     default: return fail(SFFT_ERR_PARAM, "stage must be 0, 1 or 2");
   }
   if (e != hipSuccess) return hip_fail(hipError_t(e), "stage launch");

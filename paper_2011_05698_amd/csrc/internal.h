@@ -71,6 +71,14 @@ struct SignalDesc {
   uint32_t pad;
 };
 
+// How the stage kernels receive signal descriptors: a batch table in device
+// memory (uploaded by the host), or one descriptor by value in the kernel
+// arguments for single-signal calls.
+struct SigArg {
+  const SignalDesc* table;  // batch descriptor table, or nullptr
+  SignalDesc one;           // the signal of a single-signal call
+};
+
 // Work items of the stage kernels.
 struct FoldTile {                  // fold of buckets [b0, b0 + tile) of round j of iteration m
   uint32_t sig;
@@ -116,10 +124,9 @@ void set_last_error(const std::string& s);
 // Stage launchers (kernels.hip).  Each returns hipSuccess or the launch error.
 // All signals of one launch share dtype and the Kahan setting.
 constexpr int kFoldTile = 256;      // buckets per fold work item (one thread each)
-int launch_fold(int dtype, int kahan, const SignalDesc* d_sigs, const FoldTile* d_tiles, uint32_t ntiles,
-                void* stream);
-int launch_bucket_fft(int dtype, const SignalDesc* d_sigs, const RoundItem* d_items, uint32_t nitems,
-                      uint32_t max_B, void* stream);
-int launch_recover(int dtype, const SignalDesc* d_sigs, uint32_t nsig, void* stream);
+int launch_fold(int dtype, int kahan, const SigArg& sig, const FoldTile* d_tiles, uint32_t ntiles, void* stream);
+int launch_bucket_fft(int dtype, const SigArg& sig, const RoundItem* d_items, uint32_t nitems, uint32_t max_B,
+                      void* stream);
+int launch_recover(int dtype, const SigArg& sig, uint32_t nsig, void* stream);
 
 }  // namespace sfft
