@@ -247,6 +247,9 @@ sfft_status build_host_plan(HostPlan& hp, int64_t N, int64_t K, int64_t B, int64
   while (sc < std::max(cap, bm)) sc <<= 1;
   pd.sort_cap = uint32_t(sc);
   pd.fp64_phase = N >= (int64_t(1) << 24) ? 1u : 0u;
+  uint32_t lh = 1;
+  while ((uint64_t(1) << lh) < 2 * cap) ++lh;
+  pd.log_hcap = lh;
   pd.y_total = y_off;
   pd.eta = opt.eta;
   pd.rho = opt.rho;
@@ -264,16 +267,14 @@ void layout_workspace(HostPlan& hp) {
     return o;
   };
   pd.off_y = take(pd.y_total * 2 * rs);
-  pd.off_recf0 = take(uint64_t(pd.rec_cap) * 4);
-  pd.off_recf1 = take(uint64_t(pd.rec_cap) * 4);
-  pd.off_recv0 = take(uint64_t(pd.rec_cap) * 2 * rs);
-  pd.off_recv1 = take(uint64_t(pd.rec_cap) * 2 * rs);
+  pd.off_recf = take(uint64_t(pd.rec_cap) * 4);
+  pd.off_recv = take(uint64_t(pd.rec_cap) * 2 * rs);
+  pd.off_htkey = take((uint64_t(1) << pd.log_hcap) * 4);
+  pd.off_htidx = take((uint64_t(1) << pd.log_hcap) * 4);
   pd.off_candu = take(uint64_t(pd.Bmax) * 4);
   pd.off_candd = take(uint64_t(pd.Bmax) * 4);
   pd.off_candv = take(uint64_t(pd.Bmax) * 2 * rs);
   pd.off_pairs = take(uint64_t(pd.pair_cap) * 4);
-  pd.off_cnt = take(uint64_t(pd.Bmax) * 4);
-  pd.off_start = take(uint64_t(pd.Bmax) * 4);
   pd.off_keys = take(uint64_t(pd.sort_cap) * 16);
   pd.off_p0 = take(uint64_t(pd.Bmax) * rs);
   pd.ws_bytes = off;

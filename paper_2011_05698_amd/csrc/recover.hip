@@ -4,14 +4,18 @@
 //   singleton detection, multiscale location (Eq. 15-19) and verification,
 //   median estimation (Eq. 14 per round), dedupe, accumulation
 //   rec[f] += v (step 5); finally the K largest coefficients.
-// Per-bucket work is one thread per bucket.  No private (scratch) arrays:
-// per-bucket round values live in registers through compile-time-indexed
-// sorting networks.  Counting of (coefficient, bucket) pairs uses LDS atomics.
+// One thread per bucket for the per-bucket work.  The recovered store is an
+// append-only array with an open-addressing hash index on the frequency, so an
+// iteration's survivors go straight in; every sum that depends on the store's
+// order (per-bucket subtraction, top-K) is taken in frequency order, so results
+// are bit-reproducible.  No private (scratch) arrays; wave-level scans and an
+// LDS radix select keep the number of workgroup barriers low.
 #include "device_common.h"
 
 namespace sfft {
 
-constexpr int kRecThreads = 256;
+constexpr int kRecThreads = 256;    // 4 waves; the radix select assumes >= 256
+constexpr int kWaves = kRecThreads / 64;
 constexpr int kLdsBytes = 32768;    // one buffer, reused phase by phase
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr int kRegRounds = 16;      // rounds whose estimates are sorted in registers
@@ -45,23 +49,41 @@ __device__ void block_bitonic_sort(Key* keys, uint32_t n) {
   }
 }
 
-// In-place exclusive prefix sum of a[0..n) by the whole block; returns the total.
-__device__ uint32_t block_scan_exclusive(uint32_t* a, uint32_t n, uint32_t* sh) {
-  const uint32_t T = blockDim.x, tid = threadIdx.x;
-  const uint32_t chunk = (n + T - 1) / T;
-  const uint32_t lo = min(n, tid * chunk), hi = min(n, lo + chunk);
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  const uint32_t lane = threadIdx.x & 63;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t t = __shfl_up(v, off, 64);
+    if (lane >= uint32_t(off)) v += t;
+  }
+  return v;
+}
+
+// Exclusive prefix of one value per thread across the block; *total gets the sum.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* wsum, uint32_t* total) {
+  const uint32_t incl = wave_incl_scan(v);
+  const uint32_t wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 63) wsum[wave] = incl;
+  __syncthreads();
+  uint32_t before = 0, tot = 0;
+  for (uint32_t w = 0; w < blockDim.x / 64; ++w) {
+    const uint32_t s = wsum[w];
+    before += w < wave ? s : 0u;
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return before + incl - v;
+}
+
+// In-place exclusive prefix sum of a[0..n) (contiguous chunk per thread); returns the total.
+__device__ uint32_t block_scan_array(uint32_t* a, uint32_t n, uint32_t* wsum) {
+  const uint32_t chunk = (n + blockDim.x - 1) / blockDim.x;
+  const uint32_t lo = min(n, threadIdx.x * chunk), hi = min(n, lo + chunk);
   uint32_t s = 0;
   for (uint32_t i = lo; i < hi; ++i) s += a[i];
-  sh[tid] = s;
-  __syncthreads();
-  for (uint32_t off = 1; off < T; off <<= 1) {
-    const uint32_t v = tid >= off ? sh[tid - off] : 0u;
-    __syncthreads();
-    sh[tid] += v;
-    __syncthreads();
-  }
-  const uint32_t total = sh[T - 1];
-  uint32_t run = tid ? sh[tid - 1] : 0u;
+  uint32_t total;
+  uint32_t run = block_excl_scan(s, wsum, &total);
   for (uint32_t i = lo; i < hi; ++i) {
     const uint32_t v = a[i];
     a[i] = run;
@@ -72,12 +94,12 @@ __device__ uint32_t block_scan_exclusive(uint32_t* a, uint32_t n, uint32_t* sh) 
 }
 
 template <typename V>
-__device__ V block_reduce_max(V v, V* sh) {
+__device__ V block_max(V v, V* sh) {
   for (int off = 32; off > 0; off >>= 1) {
     const V o = __shfl_xor(v, off, 64);
     v = v > o ? v : o;
   }
-  if (threadIdx.x % 64 == 0) sh[threadIdx.x / 64] = v;
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
   V r = sh[0];
   for (uint32_t w = 1; w < blockDim.x / 64; ++w) r = r > sh[w] ? r : sh[w];
@@ -85,9 +107,23 @@ __device__ V block_reduce_max(V v, V* sh) {
   return r;
 }
 
-__device__ uint32_t block_reduce_sum(uint32_t v, uint32_t* sh) {
+template <typename V>
+__device__ V block_min(V v, V* sh) {
+  for (int off = 32; off > 0; off >>= 1) {
+    const V o = __shfl_xor(v, off, 64);
+    v = o < v ? o : v;
+  }
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  V r = sh[0];
+  for (uint32_t w = 1; w < blockDim.x / 64; ++w) r = sh[w] < r ? sh[w] : r;
+  __syncthreads();
+  return r;
+}
+
+__device__ uint32_t block_sum(uint32_t v, uint32_t* sh) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  if (threadIdx.x % 64 == 0) sh[threadIdx.x / 64] = v;
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
   uint32_t r = 0;
   for (uint32_t w = 0; w < blockDim.x / 64; ++w) r += sh[w];
@@ -95,25 +131,57 @@ __device__ uint32_t block_reduce_sum(uint32_t v, uint32_t* sh) {
   return r;
 }
 
+// The k-th smallest (0-based) of n unsigned keys, by most-significant-digit
+// radix selection (8-bit digits); the block must have at least 256 threads.
+template <typename K>
+__device__ K block_select(const K* keys, uint32_t n, uint32_t k, uint32_t* hist, uint32_t* wsum, uint32_t* sel) {
+  K prefix = 0, mask = 0;
+  uint32_t r = k;
+  for (int shift = int(sizeof(K) * 8) - 8; shift >= 0; shift -= 8) {
+    if (threadIdx.x < 256) hist[threadIdx.x] = 0;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+      const K key = keys[i];
+      if ((key & mask) == prefix) atomicAdd(&hist[uint32_t(key >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    const uint32_t c = threadIdx.x < 256 ? hist[threadIdx.x] : 0u;
+    uint32_t total;
+    const uint32_t before = block_excl_scan(c, wsum, &total);
+    if (threadIdx.x < 256 && before <= r && r < before + c) {
+      sel[0] = threadIdx.x;
+      sel[1] = r - before;
+    }
+    __syncthreads();
+    const uint32_t d = sel[0];
+    r = sel[1];
+    __syncthreads();
+    prefix |= K(d) << shift;
+    mask |= K(255) << shift;
+  }
+  return prefix;
+}
+
 __device__ __forceinline__ int64_t floor_div(int64_t a, int64_t b) {  // b > 0
   return a >= 0 ? a / b : -((-a + b - 1) / b);
 }
 
-__device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t* a, uint32_t n, uint32_t v) {
-  uint32_t lo = 0, hi = n;
-  while (lo < hi) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (a[mid] < v) lo = mid + 1; else hi = mid;
-  }
-  return lo;
+// Hash index of the recovered store: frequency -> entry, linear probing.
+// Keys are read with L1-bypassing atomic loads (slots are claimed by atomics).
+__device__ __forceinline__ uint32_t hslot(uint32_t f, uint32_t logh) { return (f * 0x9E3779B1u) >> (32 - logh); }
+__device__ __forceinline__ uint32_t hkey(const uint32_t* hk, uint32_t h) {
+  return __hip_atomic_load(hk + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ uint32_t lower_bound_u64(const uint64_t* a, uint32_t n, uint64_t v) {
-  uint32_t lo = 0, hi = n;
-  while (lo < hi) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (a[mid] < v) lo = mid + 1; else hi = mid;
+__device__ uint32_t ht_find(const uint32_t* hk, const uint32_t* hi, uint32_t f, uint32_t logh) {
+  const uint32_t m = (1u << logh) - 1;
+  uint32_t h = hslot(f, logh);
+  for (uint32_t probe = 0; probe <= m; ++probe) {
+    const uint32_t k = hkey(hk, h);
+    if (k == f) return hi[h];
+    if (k == kNone) return kNone;
+    h = (h + 1) & m;
   }
-  return lo;
+  return kNone;
 }
 
 // Circular distance between two binary angles (2^64 = one turn).
@@ -321,30 +389,37 @@ struct RealKey<double> {
 template <typename R>
 struct TopKey;
 template <>
-struct TopKey<float> {
+struct TopKey<float> {  // descending magnitude, then ascending frequency
   using T = uint64_t;
-  static __device__ __forceinline__ T make(float mag2, uint32_t k) {
-    return (uint64_t(~__float_as_uint(mag2)) << 32) | k;
+  static __device__ __forceinline__ T make(float mag2, uint32_t f) {
+    return (uint64_t(~__float_as_uint(mag2)) << 32) | f;
   }
   static __device__ __forceinline__ T none() { return ~uint64_t(0); }
-  static __device__ __forceinline__ uint32_t index(T key) { return uint32_t(key); }
+  static __device__ __forceinline__ uint32_t freq(T key) { return uint32_t(key); }
+  static __device__ __forceinline__ T by_freq(uint32_t f) { return uint64_t(f); }
+  static __device__ __forceinline__ uint32_t freq_of_sorted(T key) { return uint32_t(key); }
 };
 template <>
 struct TopKey<double> {
   using T = K128;
-  static __device__ __forceinline__ T make(double mag2, uint32_t k) {
-    return K128{~uint64_t(__double_as_longlong(mag2)), uint64_t(k)};
+  static __device__ __forceinline__ T make(double mag2, uint32_t f) {
+    return K128{~uint64_t(__double_as_longlong(mag2)), uint64_t(f)};
   }
   static __device__ __forceinline__ T none() { return K128{~uint64_t(0), ~uint64_t(0)}; }
-  static __device__ __forceinline__ uint32_t index(T key) { return uint32_t(key.lo); }
+  static __device__ __forceinline__ uint32_t freq(T key) { return uint32_t(key.lo); }
+  static __device__ __forceinline__ T by_freq(uint32_t f) { return K128{uint64_t(f), 0}; }
+  static __device__ __forceinline__ uint32_t freq_of_sorted(T key) { return uint32_t(key.hi); }
 };
 
 template <typename R>
 __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
   __shared__ __attribute__((aligned(16))) unsigned char lds_buf[kLdsBytes];
-  __shared__ uint32_t sh_scan[kRecThreads];
-  __shared__ R sh_red[kRecThreads / 64];
-  __shared__ uint32_t sh_ured[kRecThreads / 64];
+  __shared__ uint32_t hist[256];
+  __shared__ uint32_t wsum[kWaves];
+  __shared__ uint32_t sel[2];
+  __shared__ uint32_t nrec_sh;
+  __shared__ R sh_red[kWaves];
+  __shared__ uint64_t sh_u64[kWaves];
   uint32_t* lds32 = reinterpret_cast<uint32_t*>(lds_buf);
   using RK = RealKey<R>;
   typename RK::T* ldskey = reinterpret_cast<typename RK::T*>(lds_buf);
@@ -354,20 +429,25 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
   const PlanDesc* pd = sd.plan;
   unsigned char* ws = reinterpret_cast<unsigned char*>(sd.ws);
   cplx<R>* Yall = reinterpret_cast<cplx<R>*>(sd.y);
-  uint32_t* const recf0 = reinterpret_cast<uint32_t*>(ws + pd->off_recf0);
-  uint32_t* const recf1 = reinterpret_cast<uint32_t*>(ws + pd->off_recf1);
-  cplx<R>* const recv0 = reinterpret_cast<cplx<R>*>(ws + pd->off_recv0);
-  cplx<R>* const recv1 = reinterpret_cast<cplx<R>*>(ws + pd->off_recv1);
+  uint32_t* rf = reinterpret_cast<uint32_t*>(ws + pd->off_recf);
+  cplx<R>* rv = reinterpret_cast<cplx<R>*>(ws + pd->off_recv);
+  uint32_t* hk = reinterpret_cast<uint32_t*>(ws + pd->off_htkey);
+  uint32_t* hi = reinterpret_cast<uint32_t*>(ws + pd->off_htidx);
   uint32_t* cand_u = reinterpret_cast<uint32_t*>(ws + pd->off_candu);
   uint32_t* cand_d = reinterpret_cast<uint32_t*>(ws + pd->off_candd);
   cplx<R>* cand_v = reinterpret_cast<cplx<R>*>(ws + pd->off_candv);
   uint32_t* pairs = reinterpret_cast<uint32_t*>(ws + pd->off_pairs);
-  uint32_t* kflag = reinterpret_cast<uint32_t*>(ws + pd->off_cnt);
-  uint64_t* keys = reinterpret_cast<uint64_t*>(ws + pd->off_keys);
+  uint64_t* gkeys = reinterpret_cast<uint64_t*>(ws + pd->off_keys);
   R* p0 = reinterpret_cast<R*>(ws + pd->off_p0);
-  const uint32_t N = pd->N, nmask = N - 1, logN = pd->logN;
-  uint32_t nrec = 0, cur = 0;
-  bool overflow = false;
+  const uint32_t N = pd->N, nmask = N - 1, logN = pd->logN, logh = pd->log_hcap;
+  const uint32_t hmask = (1u << logh) - 1;
+
+  // empty store and hash index
+  for (uint32_t h = tid; h <= hmask; h += NT) hk[h] = kNone;
+  if (tid == 0) nrec_sh = 0;
+  __threadfence();
+  __syncthreads();
+  uint32_t nrec = 0;
 
   for (uint32_t m = 0; m < pd->M; ++m) {
     const IterDesc* it = pd->iters + m;
@@ -375,10 +455,6 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
     cplx<R>* Y = Yall + it->y_off;
     const R* ghat = reinterpret_cast<const R*>(pd->ghat) + it->ghat_off;
     const uint32_t sigma = it->sigma;
-    const uint32_t* of = cur ? recf1 : recf0;
-    const cplx<R>* ov = cur ? recv1 : recv0;
-    uint32_t* nf = cur ? recf0 : recf1;
-    cplx<R>* nv = cur ? recv0 : recv1;
 
     // ---- subtraction of the coefficients recovered so far ----
     if (nrec > 0) {
@@ -386,37 +462,37 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
       for (uint32_t i = tid; i < B; i += NT) end[i] = 0;
       __syncthreads();
       for (uint32_t k = tid; k < nrec; k += NT) {
-        const int64_t u = int64_t((sigma * of[k]) & nmask);
-        const int64_t lo = -floor_div(int64_t(D) - u, L), hi = floor_div(u + int64_t(D), L);
-        for (int64_t i = lo; i <= hi; ++i) atomicAdd(&end[uint32_t(i) & (B - 1)], 1u);
+        const int64_t u = int64_t((sigma * rf[k]) & nmask);
+        const int64_t lo = -floor_div(int64_t(D) - u, L), hi2 = floor_div(u + int64_t(D), L);
+        for (int64_t i = lo; i <= hi2; ++i) atomicAdd(&end[uint32_t(i) & (B - 1)], 1u);
       }
       __syncthreads();
-      block_scan_exclusive(end, B, sh_scan);
+      block_scan_array(end, B, wsum);
       for (uint32_t k = tid; k < nrec; k += NT) {
-        const int64_t u = int64_t((sigma * of[k]) & nmask);
-        const int64_t lo = -floor_div(int64_t(D) - u, L), hi = floor_div(u + int64_t(D), L);
-        for (int64_t i = lo; i <= hi; ++i) pairs[atomicAdd(&end[uint32_t(i) & (B - 1)], 1u)] = k;
+        const int64_t u = int64_t((sigma * rf[k]) & nmask);
+        const int64_t lo = -floor_div(int64_t(D) - u, L), hi2 = floor_div(u + int64_t(D), L);
+        for (int64_t i = lo; i <= hi2; ++i) pairs[atomicAdd(&end[uint32_t(i) & (B - 1)], 1u)] = k;
       }
       __syncthreads();
       for (uint32_t i = tid; i < B; i += NT) {
         const uint32_t s0 = i ? end[i - 1] : 0u, e0 = end[i];
+        if (e0 == s0) continue;
         for (uint32_t a = s0 + 1; a < e0; ++a) {  // entries in frequency order
-          const uint32_t v = pairs[a];
+          const uint32_t v = pairs[a], fv = rf[v];
           uint32_t b = a;
-          while (b > s0 && pairs[b - 1] > v) {
+          while (b > s0 && rf[pairs[b - 1]] > fv) {
             pairs[b] = pairs[b - 1];
             --b;
           }
           pairs[b] = v;
         }
-        if (e0 == s0) continue;
         for (uint32_t j = 0; j < R1; ++j) {
           cplx<R> acc{0, 0};
           for (uint32_t q = s0; q < e0; ++q) {
             const uint32_t k = pairs[q];
-            const uint32_t u = (sigma * of[k]) & nmask;
+            const uint32_t u = (sigma * rf[k]) & nmask;
             const uint32_t d1 = (i * L - u) & nmask;
-            const cplx<R> vg = cscale(ov[k], ghat[min(d1, N - d1)]);
+            const cplx<R> vg = cscale(rv[k], ghat[min(d1, N - d1)]);
             acc = cadd(acc, cmul(vg, expi<R>((it->T[j] * u) & nmask, logN, R(-1))));
           }
           Y[size_t(j) * B + i] = csub(Y[size_t(j) * B + i], acc);
@@ -441,13 +517,22 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
       }
       cand_u[i] = cons;
     }
-    mx = block_reduce_max(mx, sh_red);
-    block_bitonic_sort(ldskey, B);
-    const R med = (RK::value(ldskey[B / 2 - 1]) + RK::value(ldskey[B / 2])) * R(0.5);
+    mx = block_max(mx, sh_red);
+    // median of the B powers: the two middle order statistics
+    const typename RK::T ka = block_select(ldskey, B, B / 2 - 1, hist, wsum, sel);
+    uint32_t le = 0;
+    typename RK::T above = ~typename RK::T(0);
+    for (uint32_t i = tid; i < B; i += NT) {
+      const typename RK::T kk = ldskey[i];
+      le += kk <= ka ? 1u : 0u;
+      if (kk > ka && kk < above) above = kk;
+    }
+    le = block_sum(le, wsum);
+    const typename RK::T kb = le >= B / 2 + 1 ? ka : block_min(above, reinterpret_cast<typename RK::T*>(sh_u64));
+    const R med = (RK::value(ka) + RK::value(kb)) * R(0.5);
     const R thr_noise = R(2.0 * it->log_B) * (med / R(0.69314718055994530942));
     const R thr_floor = R(pd->eta * pd->eta) * mx;
     const R thr = thr_noise > thr_floor ? thr_noise : thr_floor;
-    __syncthreads();
 
     // ---- location, verification, median estimation ----
     for (uint32_t i = tid; i < B; i += NT) {
@@ -467,110 +552,83 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
     }
     __syncthreads();
 
-    // ---- dedupe: one candidate per position, nearest bucket centre wins ----
+    // ---- dedupe (nearest bucket centre wins) and rec[f] += v ----
     for (uint32_t i = tid; i < B; i += NT) {
       const uint32_t u = cand_u[i];
-      uint32_t keep = 0;
-      if (u != kNone) {
-        keep = 1;
-        const uint32_t d = cand_d[i];
-        for (uint32_t dd = 1; dd <= it->reach; ++dd) {
-          const uint32_t i1 = (i - dd) & (B - 1), i2 = (i + dd) & (B - 1);
-          if (i1 != i && cand_u[i1] == u && (cand_d[i1] < d || (cand_d[i1] == d && i1 < i))) keep = 0;
-          if (i2 != i && cand_u[i2] == u && (cand_d[i2] < d || (cand_d[i2] == d && i2 < i))) keep = 0;
+      if (u == kNone) continue;
+      const uint32_t d = cand_d[i];
+      bool keep = true;
+      for (uint32_t dd = 1; dd <= it->reach; ++dd) {
+        const uint32_t i1 = (i - dd) & (B - 1), i2 = (i + dd) & (B - 1);
+        if (i1 != i && cand_u[i1] == u && (cand_d[i1] < d || (cand_d[i1] == d && i1 < i))) keep = false;
+        if (i2 != i && cand_u[i2] == u && (cand_d[i2] < d || (cand_d[i2] == d && i2 < i))) keep = false;
+      }
+      if (!keep) continue;
+      const uint32_t f = (it->sigma_inv * u) & nmask;
+      const cplx<R> v = cand_v[i];
+      uint32_t h = hslot(f, logh);
+      for (uint32_t probe = 0; probe <= hmask; ++probe) {
+        const uint32_t k = hkey(hk, h);
+        if (k == f) {  // seen in an earlier iteration
+          const uint32_t e = hi[h];
+          rv[e] = cadd(rv[e], v);
+          break;
         }
-      }
-      lds32[i] = keep;
-      kflag[i] = keep;
-    }
-    __syncthreads();
-    const uint32_t nsurv = block_scan_exclusive(lds32, B, sh_scan);
-    uint32_t npow = 1;
-    while (npow < nsurv) npow <<= 1;
-    for (uint32_t i = tid; i < B; i += NT) {
-      if (kflag[i]) {
-        const uint32_t f = (it->sigma_inv * cand_u[i]) & nmask;
-        keys[lds32[i]] = (uint64_t(f) << 32) | i;
-      }
-    }
-    for (uint32_t c = nsurv + tid; c < npow; c += NT) keys[c] = ~uint64_t(0);
-    __syncthreads();
-    if (nsurv > 1) block_bitonic_sort(keys, npow);
-
-    // ---- accumulate into the frequency-sorted store: rec[f] += v ----
-    for (uint32_t c = tid; c < nsurv; c += NT) {
-      const uint32_t f = uint32_t(keys[c] >> 32);
-      const uint32_t pos = lower_bound_u32(of, nrec, f);
-      pairs[c] = (pos < nrec && of[pos] == f) ? 0u : 1u;
-    }
-    __syncthreads();
-    const uint32_t nnew = block_scan_exclusive(pairs, nsurv, sh_scan);
-    if (nrec + nnew > pd->rec_cap) {
-      overflow = true;
-      break;
-    }
-    for (uint32_t k = tid; k < nrec; k += NT) {
-      const uint32_t f = of[k];
-      const uint32_t r = lower_bound_u64(keys, nsurv, uint64_t(f) << 32);
-      const uint32_t newbefore = r < nsurv ? pairs[r] : nnew;
-      cplx<R> v = ov[k];
-      if (r < nsurv && uint32_t(keys[r] >> 32) == f) v = cadd(v, cand_v[uint32_t(keys[r])]);
-      nf[k + newbefore] = f;
-      nv[k + newbefore] = v;
-    }
-    for (uint32_t c = tid; c < nsurv; c += NT) {
-      const uint32_t f = uint32_t(keys[c] >> 32);
-      const uint32_t pos = lower_bound_u32(of, nrec, f);
-      if (!(pos < nrec && of[pos] == f)) {
-        nf[pos + pairs[c]] = f;
-        nv[pos + pairs[c]] = cand_v[uint32_t(keys[c])];
+        if (k == kNone) {
+          const uint32_t prev = atomicCAS(hk + h, kNone, f);
+          if (prev == kNone) {
+            const uint32_t e = atomicAdd(&nrec_sh, 1u);
+            rf[e] = f;
+            rv[e] = v;
+            hi[h] = e;
+            break;
+          }
+        }
+        h = (h + 1) & hmask;
       }
     }
     __syncthreads();
-    nrec += nnew;
-    cur ^= 1u;
-  }
-
-  if (overflow) {
-    if (tid == 0) *sd.count = -1;
-    return;
+    nrec = nrec_sh;
+    __syncthreads();
   }
 
   // ---- top-K by magnitude, ties to the smaller frequency; output by frequency ----
-  const uint32_t* rf = cur ? recf1 : recf0;
-  const cplx<R>* rv = cur ? recv1 : recv0;
   using TK = TopKey<R>;
-  typename TK::T* tk = reinterpret_cast<typename TK::T*>(keys);
   uint32_t npow = 1;
   while (npow < nrec) npow <<= 1;
+  const bool in_lds = npow * sizeof(typename TK::T) <= uint32_t(kLdsBytes);
+  typename TK::T* tk = in_lds ? reinterpret_cast<typename TK::T*>(lds_buf) : reinterpret_cast<typename TK::T*>(gkeys);
   uint32_t nz = 0;
   for (uint32_t k = tid; k < npow; k += NT) {
     if (k < nrec) {
       const cplx<R> v = rv[k];
       const R mag2 = v.re * v.re + v.im * v.im;
-      tk[k] = mag2 != R(0) ? TK::make(mag2, k) : TK::none();
+      tk[k] = mag2 != R(0) ? TK::make(mag2, rf[k]) : TK::none();
       nz += mag2 != R(0) ? 1u : 0u;
-      pairs[k] = 0;
     } else {
       tk[k] = TK::none();
     }
   }
-  nz = block_reduce_sum(nz, sh_ured);
+  nz = block_sum(nz, wsum);
   if (npow > 1) block_bitonic_sort(tk, npow);
   const uint32_t Kp = min(pd->K, nz);
-  for (uint32_t c = tid; c < Kp; c += NT) pairs[TK::index(tk[c])] = 1u;
-  __syncthreads();
-  const uint32_t nsel = block_scan_exclusive(pairs, nrec, sh_scan);  // == Kp: indices are unique
-  cplx<R>* outv = reinterpret_cast<cplx<R>*>(sd.val);
-  for (uint32_t k = tid; k < nrec; k += NT) {
-    const uint32_t slot = pairs[k];
-    const uint32_t next = k + 1 < nrec ? pairs[k + 1] : nsel;
-    if (next != slot) {  // selected
-      sd.idx[slot] = int64_t(rf[k]);
-      outv[slot] = rv[k];
-    }
+  // the selected frequencies, sorted ascending
+  uint32_t kpow = 1;
+  while (kpow < Kp) kpow <<= 1;
+  for (uint32_t c = tid; c < kpow; c += NT) {  // each thread rewrites only its own slots
+    const typename TK::T key = c < Kp ? TK::by_freq(TK::freq(tk[c])) : TK::none();
+    tk[c] = key;
   }
-  if (tid == 0) *sd.count = int64_t(nsel);
+  __syncthreads();
+  if (kpow > 1) block_bitonic_sort(tk, kpow);
+  cplx<R>* outv = reinterpret_cast<cplx<R>*>(sd.val);
+  for (uint32_t c = tid; c < Kp; c += NT) {
+    const uint32_t f = TK::freq_of_sorted(tk[c]);
+    const uint32_t e = ht_find(hk, hi, f, logh);
+    sd.idx[c] = int64_t(f);
+    outv[c] = e != kNone ? rv[e] : cplx<R>{0, 0};
+  }
+  if (tid == 0) *sd.count = int64_t(Kp);
 }
 
 int launch_recover(int dtype, const SigArg& sig, uint32_t nsig, void* stream) {
