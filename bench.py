@@ -113,6 +113,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dense", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default fold launch shape")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB a few times (scales HBM byte counters)")
     args = ap.parse_args()
@@ -162,6 +163,13 @@ def main():
 
     batch.execute(xs, scales=scales, outs=outs)      # binds buffers, builds the graph
     torch.cuda.synchronize()
+    fold_cfg = None
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        fold_cfg = batch.autotune()
+        log(f"fold autotune: {fold_cfg} in {time.perf_counter() - t0:.1f}s")
+        batch.execute(xs, scales=scales, outs=outs)  # re-captures with the chosen launch shape
+        torch.cuda.synchronize()
     for _ in range(args.warmup):
         batch.execute(xs, scales=scales, outs=outs)
     torch.cuda.synchronize()
@@ -275,6 +283,7 @@ def main():
         "stage_ms": {"fold": round(stage_ms[0], 4), "bucket_fft": round(stage_ms[1], 4),
                      "recover": round(stage_ms[2], 4)},
         "graph_ms_per_step": round(graph_ms, 4),
+        "fold_launch": fold_cfg,
     }
     print(json.dumps(line), flush=True)
 

@@ -208,6 +208,36 @@ sfft_status sfft_execute_batch(sfft_batch_t b, const void* const* h_x, const flo
  */
 sfft_status sfft_batch_launch_stage(sfft_batch_t b, int32_t stage, void* stream);
 
+/*
+ * Launch shape of the fold stage (the permuted gather): taps fetched per
+ * thread before use (unroll: 8, 16 or 24), and a cap on resident workgroups
+ * per compute unit (wg_per_cu: 0 for none, else 2..8) that bounds how many
+ * signals are gathered at once.  Shapes never change results.
+ */
+typedef struct {
+  int32_t unroll;
+  int32_t wg_per_cu;
+  double fold_ms;   /* filled by sfft_batch_autotune: mean fold time of the winner */
+} sfft_fold_config;
+
+/* SFFT_ERR_PARAM for a shape outside the list above (fold_ms is ignored).
+ * The batch form waits for the device when the batch already holds a
+ * captured graph, drops it, and captures again on the next
+ * sfft_execute_batch; bound buffers stay bound. */
+sfft_status sfft_plan_set_fold_config(sfft_plan_t p, const sfft_fold_config* cfg);
+sfft_status sfft_batch_set_fold_config(sfft_batch_t b, const sfft_fold_config* cfg);
+
+/*
+ * sfft_batch_autotune -- time the fold stage of the bound batch (buffers
+ * bound by a prior sfft_execute_batch) for every unroll x wg_per_cu
+ * candidate on `stream`, keep the fastest and report it in *best.  Blocks
+ * until the timing launches finish.  The timing launches overwrite the
+ * batch's bucket workspace only (outputs are untouched); the batch's graph
+ * is captured again by the next sfft_execute_batch.  SFFT_ERR_STATE when no
+ * buffers are bound.
+ */
+sfft_status sfft_batch_autotune(sfft_batch_t b, void* stream, sfft_fold_config* best);
+
 sfft_status sfft_batch_destroy(sfft_batch_t b);
 
 const char* sfft_status_string(sfft_status s);

@@ -28,6 +28,7 @@ struct sfft_plan_s {
   RoundItem* d_items = nullptr;
   unsigned char* d_ws = nullptr;
   uint32_t ntiles = 0, nitems = 0;
+  FoldConfig fold{8, 0};
 };
 
 struct sfft_batch_s {
@@ -45,6 +46,7 @@ struct sfft_batch_s {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipStream_t capture_stream = nullptr;
+  FoldConfig fold{8, 0};
 };
 
 namespace {
@@ -61,14 +63,20 @@ sfft_status hip_fail(hipError_t e, const char* what) {
 
 uint64_t align256(uint64_t v) { return (v + 255) & ~uint64_t(255); }
 
+// Work lists of one signal, signal-major: the fold covers the (R_m+1) x B_m
+// (round, bucket) items of every iteration in tiles of kFoldTile items.
 void build_work_lists(const HostPlan& hp, uint32_t sig, std::vector<FoldTile>& tiles, std::vector<RoundItem>& items) {
   for (int m = 0; m < hp.loops; ++m) {
     const IterDesc& d = hp.iters[m].d;
-    for (uint32_t j = 0; j <= d.R; ++j) {
-      items.push_back(RoundItem{sig, uint16_t(m), uint16_t(j)});
-      for (uint32_t b0 = 0; b0 < d.B; b0 += kFoldTile) tiles.push_back(FoldTile{sig, uint16_t(m), uint16_t(j), b0});
-    }
+    for (uint32_t j = 0; j <= d.R; ++j) items.push_back(RoundItem{sig, uint16_t(m), uint16_t(j)});
+    const uint32_t n = (d.R + 1) * d.B;
+    for (uint32_t i0 = 0; i0 < n; i0 += kFoldTile) tiles.push_back(FoldTile{sig, uint32_t(m), i0});
   }
+}
+
+bool valid_fold(const sfft_fold_config* c) {
+  return c && (c->unroll == 8 || c->unroll == 16 || c->unroll == 24) && c->wg_per_cu >= 0 && c->wg_per_cu <= 8 &&
+         c->wg_per_cu != 1;
 }
 
 // Uploads tables and descriptors of a plan and allocates its one-signal workspace.
@@ -189,7 +197,7 @@ uint32_t max_B(const HostPlan& hp) {
 }
 
 sfft_status run_hash(sfft_plan_t p, const SigArg& a, hipStream_t s) {
-  int e = launch_fold(p->hp.dtype, p->hp.kahan, a, p->d_tiles, p->ntiles, s);
+  int e = launch_fold(p->hp.dtype, p->hp.kahan, p->fold, a, p->d_tiles, p->ntiles, s);
   if (e != hipSuccess) return hip_fail(hipError_t(e), "fold launch");
   e = launch_bucket_fft(p->hp.dtype, a, p->d_items, p->nitems, max_B(p->hp), s);
   if (e != hipSuccess) return hip_fail(hipError_t(e), "bucket FFT launch");
@@ -368,6 +376,7 @@ sfft_status sfft_batch_create(sfft_batch_t* out, const sfft_plan_t* h_plans, int
   b->plans.assign(h_plans, h_plans + n);
   b->dtype = h_plans[0]->hp.dtype;
   b->kahan = h_plans[0]->hp.kahan;
+  b->fold = h_plans[0]->fold;
   std::vector<FoldTile> tiles;
   std::vector<RoundItem> items;
   uint64_t ws = 0;
@@ -432,24 +441,24 @@ sfft_status sfft_execute_batch(sfft_batch_t b, const void* const* h_x, const flo
     if (e != hipSuccess) return hip_fail(e, "batch descriptor upload");
     b->bound = sig;
     b->has_binding = true;
-    if (!b->exec) {
-      hipStream_t cs = b->capture_stream;
-      e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-      if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-      const SigArg a = table_arg(b);
-      int le = launch_fold(b->dtype, b->kahan, a, b->d_tiles, b->ntiles, cs);
-      if (le == hipSuccess) le = launch_bucket_fft(b->dtype, a, b->d_items, b->nitems, b->max_B, cs);
-      if (le == hipSuccess) le = launch_recover(b->dtype, a, uint32_t(n), cs);
-      hipGraph_t g = nullptr;
-      hipError_t ee = hipStreamEndCapture(cs, &g);
-      if (le != hipSuccess) return hip_fail(hipError_t(le), "batch capture launch");
-      if (ee != hipSuccess) return hip_fail(ee, "hipStreamEndCapture");
-      b->graph = g;
-      ee = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
-      if (ee != hipSuccess) {
-        b->exec = nullptr;
-        return hip_fail(ee, "hipGraphInstantiate");
-      }
+  }
+  if (!b->exec) {  // first execute, or the launch shape changed: capture the three stages
+    hipStream_t cs = b->capture_stream;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    const SigArg a = table_arg(b);
+    int le = launch_fold(b->dtype, b->kahan, b->fold, a, b->d_tiles, b->ntiles, cs);
+    if (le == hipSuccess) le = launch_bucket_fft(b->dtype, a, b->d_items, b->nitems, b->max_B, cs);
+    if (le == hipSuccess) le = launch_recover(b->dtype, a, uint32_t(n), cs);
+    hipGraph_t g = nullptr;
+    hipError_t ee = hipStreamEndCapture(cs, &g);
+    if (le != hipSuccess) return hip_fail(hipError_t(le), "batch capture launch");
+    if (ee != hipSuccess) return hip_fail(ee, "hipStreamEndCapture");
+    b->graph = g;
+    ee = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    if (ee != hipSuccess) {
+      b->exec = nullptr;
+      return hip_fail(ee, "hipGraphInstantiate");
     }
   }
   hipError_t e = hipGraphLaunch(b->exec, s);
@@ -464,12 +473,79 @@ sfft_status sfft_batch_launch_stage(sfft_batch_t b, int32_t stage, void* stream)
   int e;
   const SigArg a = table_arg(b);
   switch (stage) {
-    case 0: e = launch_fold(b->dtype, b->kahan, a, b->d_tiles, b->ntiles, s); break;
+    case 0: e = launch_fold(b->dtype, b->kahan, b->fold, a, b->d_tiles, b->ntiles, s); break;
     case 1: e = launch_bucket_fft(b->dtype, a, b->d_items, b->nitems, b->max_B, s); break;
     case 2: e = launch_recover(b->dtype, a, uint32_t(b->plans.size()), s); break;
     default: return fail(SFFT_ERR_PARAM, "stage must be 0, 1 or 2");
   }
   if (e != hipSuccess) return hip_fail(hipError_t(e), "stage launch");
+  return SFFT_OK;
+}
+
+sfft_status sfft_plan_set_fold_config(sfft_plan_t p, const sfft_fold_config* cfg) {
+  if (!p || !valid_fold(cfg)) return fail(SFFT_ERR_PARAM, "invalid fold configuration");
+  p->fold = FoldConfig{cfg->unroll, cfg->wg_per_cu};
+  return SFFT_OK;
+}
+
+sfft_status sfft_batch_set_fold_config(sfft_batch_t b, const sfft_fold_config* cfg) {
+  if (!b || !valid_fold(cfg)) return fail(SFFT_ERR_PARAM, "invalid fold configuration");
+  b->fold = FoldConfig{cfg->unroll, cfg->wg_per_cu};
+  if (b->exec || b->graph) {
+    // the captured graph holds the old kernel choice: let any replay in
+    // flight end, drop the graph, and capture again on the next execute
+    const hipError_t e = hipDeviceSynchronize();
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+  }
+  return SFFT_OK;
+}
+
+sfft_status sfft_batch_autotune(sfft_batch_t b, void* stream, sfft_fold_config* best) {
+  if (!b) return fail(SFFT_ERR_PARAM, "null batch");
+  if (!b->has_binding) return fail(SFFT_ERR_STATE, "no buffers bound: call sfft_execute_batch first");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const SigArg a = table_arg(b);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return fail(SFFT_ERR_LAUNCH, "hipEventCreate");
+  const int unrolls[3] = {8, 16, 24};
+  const int caps[5] = {0, 2, 3, 4, 6};
+  FoldConfig win = b->fold;
+  float win_ms = 1e30f;
+  sfft_status st = SFFT_OK;
+  for (int ui = 0; ui < 3 && st == SFFT_OK; ++ui) {
+    for (int ci = 0; ci < 5 && st == SFFT_OK; ++ci) {
+      const FoldConfig c{unrolls[ui], caps[ci]};
+      int le = launch_fold(b->dtype, b->kahan, c, a, b->d_tiles, b->ntiles, s);  // warm
+      float total = 0.f;
+      for (int r = 0; r < 3 && le == hipSuccess; ++r) {
+        (void)hipEventRecord(e0, s);
+        le = launch_fold(b->dtype, b->kahan, c, a, b->d_tiles, b->ntiles, s);
+        (void)hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess) le = hipErrorLaunchFailure;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        total += ms;
+      }
+      if (le != hipSuccess) {
+        st = hip_fail(hipError_t(le), "autotune launch");
+        break;
+      }
+      if (total / 3.f < win_ms) {
+        win_ms = total / 3.f;
+        win = c;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != SFFT_OK) return st;
+  sfft_fold_config out{win.unroll, win.wg_per_cu, double(win_ms)};
+  sfft_batch_set_fold_config(b, &out);
+  if (best) *best = out;
   return SFFT_OK;
 }
 

@@ -1,9 +1,11 @@
 // HashToBins, part 1 (Sec. 2.4, Lemma 1): permuted gather x[sigma (t - T) mod N]
 // (Eq. 7), window G_t (Eq. 10) and aliasing t -> t mod B (Eq. 11):
 //   y_j[b] = sum_{|t| <= h, t = b mod B} G_t x[sigma (t - T_j) mod N].
-// One thread owns one bucket b and walks its taps t = t_first + k B; the
-// sample index advances by sigma B mod N per tap.  Index arithmetic is uint32
-// with wrap-around, exact because N divides 2^32.
+// One thread owns one (round j, bucket b) item of an iteration and walks its
+// taps t = t_first + k B; the sample index advances by sigma B mod N per tap.
+// Index arithmetic is uint32 with wrap-around, exact because N divides 2^32.
+// Taps are fetched U at a time (predicated at the end) so that U independent
+// gathers are in flight per thread.
 #include "device_common.h"
 
 namespace sfft {
@@ -52,19 +54,20 @@ struct Acc {
   }
 };
 
-template <class Ld, bool KAHAN>
+template <class Ld, bool KAHAN, int U>
 __global__ __launch_bounds__(kFoldTile) void fold_kernel(SigArg arg, const FoldTile* __restrict__ tiles) {
   using R = typename Ld::R;
   const FoldTile tl = tiles[blockIdx.x];
   const SignalDesc sd = load_signal(arg, tl.sig);
   const PlanDesc* pd = sd.plan;
   const IterDesc* it = pd->iters + tl.m;
-  const uint32_t B = it->B;
-  const uint32_t b = tl.b0 + threadIdx.x;
-  if (b >= B) return;
+  const uint32_t B = it->B, logB = it->logB;
+  const uint32_t item = tl.i0 + threadIdx.x;
+  if (item >= ((it->R + 1) << logB)) return;
+  const uint32_t j = item >> logB, b = item & (B - 1);
   const uint32_t nmask = pd->N - 1;
   const int32_t h = int32_t(it->h);
-  const uint32_t T = it->T[tl.j];
+  const uint32_t T = it->T[j];
   const uint32_t sigma = it->sigma;
   const R* __restrict__ G = reinterpret_cast<const R*>(pd->window) + it->win_off;
   // first tap t = b (mod B) with t >= -h; B <= w guarantees t_first <= h
@@ -74,47 +77,60 @@ __global__ __launch_bounds__(kFoldTile) void fold_kernel(SigArg arg, const FoldT
   const uint32_t step = (sigma * B) & nmask;
   Acc<R, KAHAN> acc;
   int32_t t = tf;
-  uint32_t k = 0;
-  constexpr int U = 8;
-  for (; k + U <= ntaps; k += U) {
+  for (uint32_t k0 = 0; k0 < ntaps; k0 += U) {
     cplx<R> s[U];
     R g[U];
 #pragma unroll
     for (int q = 0; q < U; ++q) {
-      s[q] = Ld::load(sd.x, idx);
-      const int32_t tt = t + q * int32_t(B);
-      g[q] = G[tt < 0 ? -tt : tt];
+      if (k0 + q < ntaps) {
+        s[q] = Ld::load(sd.x, idx);
+        g[q] = G[t < 0 ? -t : t];
+      } else {
+        s[q] = cplx<R>{0, 0};
+        g[q] = R(0);
+      }
       idx = (idx + step) & nmask;
+      t += int32_t(B);
     }
 #pragma unroll
     for (int q = 0; q < U; ++q) acc.add(g[q], s[q]);
-    t += U * int32_t(B);
-  }
-  for (; k < ntaps; ++k) {
-    const cplx<R> s = Ld::load(sd.x, idx);
-    acc.add(G[t < 0 ? -t : t], s);
-    idx = (idx + step) & nmask;
-    t += int32_t(B);
   }
   cplx<R> out{acc.re, acc.im};
   if (Ld::kScaled) out = cscale(out, R(sd.scale));
-  cplx<R>* Y = reinterpret_cast<cplx<R>*>(sd.y) + it->y_off + size_t(tl.j) * B;
-  Y[b] = out;
+  cplx<R>* Y = reinterpret_cast<cplx<R>*>(sd.y) + it->y_off;
+  Y[item] = out;  // item = j * B + b: row j of the iteration's (R+1) x B block
 }
 
-int launch_fold(int dtype, int kahan, const SigArg& sig, const FoldTile* d_tiles, uint32_t ntiles, void* stream) {
+int fold_lds_bytes(int wg_per_cu) {
+  // 160 KiB of LDS per CU; reserving just over 1/(n+1) of it caps residency at n
+  if (wg_per_cu <= 0) return 0;
+  const int per = 163840 / (wg_per_cu + 1) + 1024;
+  return per > 65536 ? 65536 : per;
+}
+
+template <class Ld, bool KAHAN>
+static void launch_u(int unroll, dim3 grid, dim3 block, size_t lds, hipStream_t s, const SigArg& sig,
+                     const FoldTile* d_tiles) {
+  if (unroll >= 24) hipLaunchKernelGGL((fold_kernel<Ld, KAHAN, 24>), grid, block, lds, s, sig, d_tiles);
+  else if (unroll >= 16) hipLaunchKernelGGL((fold_kernel<Ld, KAHAN, 16>), grid, block, lds, s, sig, d_tiles);
+  else hipLaunchKernelGGL((fold_kernel<Ld, KAHAN, 8>), grid, block, lds, s, sig, d_tiles);
+}
+
+int launch_fold(int dtype, int kahan, const FoldConfig& cfg, const SigArg& sig, const FoldTile* d_tiles,
+                uint32_t ntiles, void* stream) {
   if (ntiles == 0) return hipSuccess;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  dim3 grid(ntiles), block(kFoldTile);
+  const dim3 grid(ntiles), block(kFoldTile);
+  const size_t lds = size_t(fold_lds_bytes(cfg.wg_per_cu));
   if (dtype == SFFT_C128) {
-    if (kahan) hipLaunchKernelGGL((fold_kernel<LoadC128, true>), grid, block, 0, s, sig, d_tiles);
-    else hipLaunchKernelGGL((fold_kernel<LoadC128, false>), grid, block, 0, s, sig, d_tiles);
+    if (kahan) launch_u<LoadC128, true>(cfg.unroll, grid, block, lds, s, sig, d_tiles);
+    else launch_u<LoadC128, false>(cfg.unroll, grid, block, lds, s, sig, d_tiles);
   } else if (dtype == SFFT_F16X2_SCALED) {
-    if (kahan) hipLaunchKernelGGL((fold_kernel<LoadF16, true>), grid, block, 0, s, sig, d_tiles);
-    else hipLaunchKernelGGL((fold_kernel<LoadF16, false>), grid, block, 0, s, sig, d_tiles);
+    if (kahan) launch_u<LoadF16, true>(cfg.unroll, grid, block, lds, s, sig, d_tiles);
+    else launch_u<LoadF16, false>(cfg.unroll, grid, block, lds, s, sig, d_tiles);
   } else {
-    if (kahan) hipLaunchKernelGGL((fold_kernel<LoadC64, true>), grid, block, 0, s, sig, d_tiles);
-    else hipLaunchKernelGGL((fold_kernel<LoadC64, false>), grid, block, 0, s, sig, d_tiles);
+    if (kahan) launch_u<LoadC64, true>(cfg.unroll, grid, block, lds, s, sig, d_tiles);
+    else launch_u<LoadC64, false>(cfg.unroll, grid, block, lds, s, sig, d_tiles);
   }
   return hipGetLastError();
 }

@@ -80,10 +80,10 @@ struct SigArg {
 };
 
 // Work items of the stage kernels.
-struct FoldTile {                  // fold of buckets [b0, b0 + tile) of round j of iteration m
+struct FoldTile {                  // fold items [i0, i0 + kFoldTile) of iteration m; item = j * B_m + b
   uint32_t sig;
-  uint16_t m, j;
-  uint32_t b0;
+  uint32_t m;
+  uint32_t i0;
 };
 struct RoundItem {                 // one (signal, iteration, round)
   uint32_t sig;
@@ -123,8 +123,19 @@ void set_last_error(const std::string& s);
 
 // Stage launchers (kernels.hip).  Each returns hipSuccess or the launch error.
 // All signals of one launch share dtype and the Kahan setting.
-constexpr int kFoldTile = 256;      // buckets per fold work item (one thread each)
-int launch_fold(int dtype, int kahan, const SigArg& sig, const FoldTile* d_tiles, uint32_t ntiles, void* stream);
+constexpr int kFoldTile = 256;      // (round, bucket) items per fold work item (one thread each)
+
+// Launch shape of the fold: taps in flight per thread, and a cap on resident
+// workgroups per CU (enforced through an LDS reservation) that bounds how many
+// signals are gathered at once, so a signal's lines stay in the last-level
+// cache between the rounds and iterations that touch them again.
+struct FoldConfig {
+  int unroll;       // 8, 16 or 24
+  int wg_per_cu;    // 0: no cap; else 2..8
+};
+int fold_lds_bytes(int wg_per_cu);
+int launch_fold(int dtype, int kahan, const FoldConfig& cfg, const SigArg& sig, const FoldTile* d_tiles,
+                uint32_t ntiles, void* stream);
 int launch_bucket_fft(int dtype, const SigArg& sig, const RoundItem* d_items, uint32_t nitems, uint32_t max_B,
                       void* stream);
 int launch_recover(int dtype, const SigArg& sig, uint32_t nsig, void* stream);

@@ -27,7 +27,7 @@ EXPORTED = [
     "sfft_default_options", "sfft_plan", "sfft_execute", "sfft_hash_to_bins", "sfft_recover",
     "sfft_get_plan_info", "sfft_get_iter_info", "sfft_plan_dump_tables", "sfft_destroy",
     "sfft_batch_create", "sfft_execute_batch", "sfft_batch_launch_stage", "sfft_batch_destroy",
-    "sfft_status_string",
+    "sfft_plan_set_fold_config", "sfft_batch_set_fold_config", "sfft_batch_autotune", "sfft_status_string",
     "sfft_last_error",
 ]
 
@@ -43,6 +43,10 @@ class Options(ctypes.Structure):
                 ("kahan", ctypes.c_int32), ("b_min", ctypes.c_int32), ("pad0", ctypes.c_int32),
                 ("eta", ctypes.c_double), ("rho", ctypes.c_double), ("flags", ctypes.c_uint32),
                 ("pad1", ctypes.c_uint32)]
+
+
+class FoldConfig(ctypes.Structure):
+    _fields_ = [("unroll", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32), ("fold_ms", ctypes.c_double)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -81,6 +85,9 @@ def _load():
         "sfft_execute_batch": (i32, [vp, ctypes.POINTER(vp), ctypes.POINTER(f32), ctypes.POINTER(vp),
                                      ctypes.POINTER(vp), vp, vp]),
         "sfft_batch_launch_stage": (i32, [vp, i32, vp]),
+        "sfft_plan_set_fold_config": (i32, [vp, ctypes.POINTER(FoldConfig)]),
+        "sfft_batch_set_fold_config": (i32, [vp, ctypes.POINTER(FoldConfig)]),
+        "sfft_batch_autotune": (i32, [vp, vp, ctypes.POINTER(FoldConfig)]),
         "sfft_batch_destroy": (i32, [vp]),
         "sfft_status_string": (ctypes.c_char_p, [i32]),
         "sfft_last_error": (ctypes.c_char_p, []),
@@ -179,6 +186,22 @@ def sfft_execute_batch(batch, xs, scales, idxs, vals, counts, stream=None):
 
 def sfft_batch_launch_stage(batch, stage, stream=None):
     _check(_lib.sfft_batch_launch_stage(batch, stage, _stream(stream)))
+
+
+def sfft_plan_set_fold_config(plan, unroll, wg_per_cu):
+    c = FoldConfig(unroll, wg_per_cu, 0.0)
+    _check(_lib.sfft_plan_set_fold_config(plan, ctypes.byref(c)))
+
+
+def sfft_batch_set_fold_config(batch, unroll, wg_per_cu):
+    c = FoldConfig(unroll, wg_per_cu, 0.0)
+    _check(_lib.sfft_batch_set_fold_config(batch, ctypes.byref(c)))
+
+
+def sfft_batch_autotune(batch, stream=None) -> dict:
+    c = FoldConfig()
+    _check(_lib.sfft_batch_autotune(batch, _stream(stream), ctypes.byref(c)))
+    return {"unroll": c.unroll, "wg_per_cu": c.wg_per_cu, "fold_ms": c.fold_ms}
 
 
 def sfft_batch_destroy(batch):
@@ -292,6 +315,14 @@ class Batch:
 
     def launch_stage(self, stage, stream=None):
         sfft_batch_launch_stage(self.handle, stage, stream)
+
+    def autotune(self, stream=None) -> dict:
+        """Time the fold stage over its launch shapes and keep the fastest
+        (needs buffers bound by a prior execute)."""
+        return sfft_batch_autotune(self.handle, stream)
+
+    def set_fold_config(self, unroll, wg_per_cu):
+        sfft_batch_set_fold_config(self.handle, unroll, wg_per_cu)
 
     def execute(self, xs, scales=None, outs=None, stream=None):
         if outs is None:

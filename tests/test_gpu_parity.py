@@ -207,6 +207,20 @@ def test_batch_uneven_matches_single(sf):
             assert np.array_equal(gv, singles[s][1].astype(np.complex64))
             assert np.array_equal(gi, oracles[s][0])
             assert rel_l2(gv.astype(np.complex128), oracles[s][1]) <= 1e-4
+    # every fold launch shape sums the taps of a bucket in the same order, so
+    # the tuned and the explicitly chosen shapes give bit-identical results
+    best = batch.autotune()
+    assert best["unroll"] in (8, 16, 24) and best["fold_ms"] > 0
+    for unroll, cap in ((8, 0), (16, 3), (24, 6)):
+        batch.set_fold_config(unroll, cap)
+        idxs, vals, counts = batch.execute(xs)
+        torch.cuda.synchronize()
+        for s in range(len(specs)):
+            c = int(counts[s].item())
+            assert np.array_equal(idxs[s][:c].cpu().numpy(), singles[s][0])
+            assert np.array_equal(vals[s][:c].cpu().numpy(), singles[s][1].astype(np.complex64))
+    with pytest.raises(sf.SfftError):
+        batch.set_fold_config(12, 0)
 
 
 def test_edge_cases(sf):
