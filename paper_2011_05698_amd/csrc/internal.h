@@ -42,7 +42,6 @@ struct PlanDesc {
   uint32_t dtype, kahan;
   uint32_t rec_cap;               // capacity of the recovered-coefficient store
   uint32_t Bmax;                  // largest B_m
-  uint32_t pair_cap;              // capacity of the (entry, bucket) list of the subtraction
   uint32_t sort_cap;              // power of two >= max(rec_cap, Bmax)
   uint32_t fp64_phase;            // take location phases in FP64 (N >= 2^24)
   uint32_t log_hcap;              // hash index of the store: 2^log_hcap >= 2 rec_cap slots
@@ -50,7 +49,7 @@ struct PlanDesc {
   uint64_t ws_bytes;              // workspace bytes per signal
   // byte offsets inside one signal's workspace
   uint64_t off_y, off_recf, off_recv, off_htkey, off_htidx, off_candu, off_candd, off_candv;
-  uint64_t off_pairs, off_keys, off_p0;
+  uint64_t off_keys, off_p0;
   double eta, rho;
   const IterDesc* iters;          // device array of M descriptors
   const void* window;             // float or double table

@@ -234,15 +234,13 @@ sfft_status build_host_plan(HostPlan& hp, int64_t N, int64_t K, int64_t B, int64
   pd.l = uint32_t(l); pd.logl = uint32_t(ilog2(l));
   pd.qn = int32_t(qn); pd.logqd = uint32_t(ilog2(qd));
   pd.dtype = uint32_t(opt.dtype); pd.kahan = uint32_t(hp.kahan);
-  uint64_t cap = 0, bm = 0, pairs = 0;
+  uint64_t cap = 0, bm = 0;
   for (auto& it : hp.iters) {
     cap += it.d.B;
     bm = std::max<uint64_t>(bm, it.d.B);
   }
-  for (auto& it : hp.iters) pairs = std::max<uint64_t>(pairs, uint64_t(it.d.reach + 1) * cap);
   pd.rec_cap = uint32_t(cap);
   pd.Bmax = uint32_t(bm);
-  pd.pair_cap = uint32_t(pairs);
   uint64_t sc = 1;
   while (sc < std::max(cap, bm)) sc <<= 1;
   pd.sort_cap = uint32_t(sc);
@@ -274,7 +272,6 @@ void layout_workspace(HostPlan& hp) {
   pd.off_candu = take(uint64_t(pd.Bmax) * 4);
   pd.off_candd = take(uint64_t(pd.Bmax) * 4);
   pd.off_candv = take(uint64_t(pd.Bmax) * 2 * rs);
-  pd.off_pairs = take(uint64_t(pd.pair_cap) * 4);
   pd.off_keys = take(uint64_t(pd.sort_cap) * 16);
   pd.off_p0 = take(uint64_t(pd.Bmax) * rs);
   pd.ws_bytes = off;

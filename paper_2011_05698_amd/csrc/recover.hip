@@ -49,6 +49,18 @@ __device__ void block_bitonic_sort(Key* keys, uint32_t n) {
   }
 }
 
+// Number of sorted keys (u << 32 | k) among the first n whose u is below x.
+__device__ __forceinline__ uint32_t sorted_lower_bound(const uint64_t* keys, uint32_t n, uint32_t x) {
+  const uint64_t t = uint64_t(x) << 32;
+  uint32_t lo = 0, hi = n;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (keys[mid] < t) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
   const uint32_t lane = threadIdx.x & 63;
 #pragma unroll
@@ -436,7 +448,6 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
   uint32_t* cand_u = reinterpret_cast<uint32_t*>(ws + pd->off_candu);
   uint32_t* cand_d = reinterpret_cast<uint32_t*>(ws + pd->off_candd);
   cplx<R>* cand_v = reinterpret_cast<cplx<R>*>(ws + pd->off_candv);
-  uint32_t* pairs = reinterpret_cast<uint32_t*>(ws + pd->off_pairs);
   uint64_t* gkeys = reinterpret_cast<uint64_t*>(ws + pd->off_keys);
   R* p0 = reinterpret_cast<R*>(ws + pd->off_p0);
   const uint32_t N = pd->N, nmask = N - 1, logN = pd->logN, logh = pd->log_hcap;
@@ -457,44 +468,54 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
     const uint32_t sigma = it->sigma;
 
     // ---- subtraction of the coefficients recovered so far ----
+    // The store is sorted by its permuted frequency u = sigma f mod N, so the
+    // coefficients that leak into bucket i (circular distance |iL - u| <= D)
+    // form one circular run of the sorted list.  Each (bucket, round) sum is
+    // split over a team of lanes sized to the mean run length and closed by
+    // a butterfly of fixed shape: the order of every sum depends only on the
+    // recovered set, not on how the store was filled.
     if (nrec > 0) {
-      uint32_t* end = lds32;  // per-bucket counts, then list ends
-      for (uint32_t i = tid; i < B; i += NT) end[i] = 0;
+      uint32_t npow = 1;
+      while (npow < nrec) npow <<= 1;
+      uint64_t* sk = npow * 8u <= uint32_t(kLdsBytes) ? reinterpret_cast<uint64_t*>(lds_buf) : gkeys;
+      for (uint32_t k = tid; k < npow; k += NT)
+        sk[k] = k < nrec ? (uint64_t((sigma * rf[k]) & nmask) << 32) | k : ~uint64_t(0);
       __syncthreads();
-      for (uint32_t k = tid; k < nrec; k += NT) {
-        const int64_t u = int64_t((sigma * rf[k]) & nmask);
-        const int64_t lo = -floor_div(int64_t(D) - u, L), hi2 = floor_div(u + int64_t(D), L);
-        for (int64_t i = lo; i <= hi2; ++i) atomicAdd(&end[uint32_t(i) & (B - 1)], 1u);
-      }
-      __syncthreads();
-      block_scan_array(end, B, wsum);
-      for (uint32_t k = tid; k < nrec; k += NT) {
-        const int64_t u = int64_t((sigma * rf[k]) & nmask);
-        const int64_t lo = -floor_div(int64_t(D) - u, L), hi2 = floor_div(u + int64_t(D), L);
-        for (int64_t i = lo; i <= hi2; ++i) pairs[atomicAdd(&end[uint32_t(i) & (B - 1)], 1u)] = k;
-      }
-      __syncthreads();
-      for (uint32_t i = tid; i < B; i += NT) {
-        const uint32_t s0 = i ? end[i - 1] : 0u, e0 = end[i];
-        if (e0 == s0) continue;
-        for (uint32_t a = s0 + 1; a < e0; ++a) {  // entries in frequency order
-          const uint32_t v = pairs[a], fv = rf[v];
-          uint32_t b = a;
-          while (b > s0 && rf[pairs[b - 1]] > fv) {
-            pairs[b] = pairs[b - 1];
-            --b;
-          }
-          pairs[b] = v;
-        }
-        for (uint32_t j = 0; j < R1; ++j) {
-          cplx<R> acc{0, 0};
-          for (uint32_t q = s0; q < e0; ++q) {
-            const uint32_t k = pairs[q];
-            const uint32_t u = (sigma * rf[k]) & nmask;
+      if (npow > 1) block_bitonic_sort(sk, npow);
+      // team size: smallest power of two >= the mean run length, in [1, 64]
+      const double mean_run = double(nrec) * double(2 * D + 1) / double(N);
+      uint32_t S = 1;
+      while (S < 64 && double(S) < mean_run) S <<= 1;
+      const uint32_t team = tid / S, lane = tid & (S - 1), nteams = NT / S;
+      const uint32_t nout = B * R1;
+      const uint32_t span = 2 * D + 1;  // < N
+      for (uint32_t base = 0; base < nout; base += nteams) {  // uniform trip count per wave
+        const uint32_t o = base + team;
+        cplx<R> acc{0, 0};
+        if (o < nout) {
+          const uint32_t i = o / R1, j = o - i * R1;
+          const uint32_t a = (i * L - D) & nmask;  // first u of the run
+          const uint64_t stop = uint64_t(a) + span;
+          const uint32_t q0 = sorted_lower_bound(sk, nrec, a);
+          const uint32_t cnt = stop <= N ? sorted_lower_bound(sk, nrec, uint32_t(stop)) - q0
+                                         : nrec - q0 + sorted_lower_bound(sk, nrec, uint32_t(stop - N));
+          const uint32_t Tj = it->T[j];
+          for (uint32_t v = lane; v < cnt; v += S) {
+            uint32_t q = q0 + v;
+            q = q >= nrec ? q - nrec : q;
+            const uint64_t key = sk[q];
+            const uint32_t u = uint32_t(key >> 32), k = uint32_t(key);
             const uint32_t d1 = (i * L - u) & nmask;
             const cplx<R> vg = cscale(rv[k], ghat[min(d1, N - d1)]);
-            acc = cadd(acc, cmul(vg, expi<R>((it->T[j] * u) & nmask, logN, R(-1))));
+            acc = cadd(acc, cmul(vg, expi<R>((Tj * u) & nmask, logN, R(-1))));
           }
+        }
+        for (uint32_t off = S >> 1; off > 0; off >>= 1) {
+          acc.re += __shfl_xor(acc.re, int(off), 64);
+          acc.im += __shfl_xor(acc.im, int(off), 64);
+        }
+        if (o < nout && lane == 0) {
+          const uint32_t i = o / R1, j = o - i * R1;
           Y[size_t(j) * B + i] = csub(Y[size_t(j) * B + i], acc);
         }
       }

@@ -66,10 +66,31 @@ class IterInfo(ctypes.Structure):
                 ("last_is_enum", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
+def _hip_runtimes():
+    """Distinct HIP runtime files mapped into this process (Linux)."""
+    try:
+        with open("/proc/self/maps") as f:
+            return sorted({os.path.realpath(ln.split()[-1]) for ln in f if "libamdhip64" in ln})
+    except OSError:
+        return []
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    # Device buffers and streams come from torch, so the library must run on
+    # the HIP runtime torch carries: loading torch first makes the loader
+    # bind libsfft's libamdhip64.so.7 to that same copy (equal soname).  Two
+    # runtimes in one process see separate device contexts.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
+    rts = _hip_runtimes()
+    if len(rts) > 1:
+        raise ImportError("two HIP runtimes are loaded (" + ", ".join(rts) + "); import torch before any "
+                          "library that links the system HIP runtime, then load libsfft")
     vp, i64, i32, f64, f32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_float
     sig = {
         "sfft_default_options": (None, [ctypes.POINTER(Options)]),
