@@ -7,6 +7,11 @@ each exactly K = 1000 sparse (support uniform without replacement, magnitude
 B = 2048 buckets, w = 45057 taps, 12 iterations, (l, q) = (16, 1),
 delta = 1e-6, plan seed 602; signal i uses seed 601 + i.
 
+Layout (default): position-major, sample c of signal s at X[c, s], so that
+every tap of the gather reads one contiguous row segment of the batch;
+--layout per-signal keeps one buffer per signal (the layout of uneven
+batches), and the other layout is timed beside the main one for context.
+
 A step is one pass of the whole hot path over the batch: the fold stage
 (permuted gather + window + fold for every round of every iteration), the
 bucket DFTs, and the recovery stage (subtraction, detection, location,
@@ -68,10 +73,10 @@ def make_batch(torch, n, N, K, snr, dtype, dev, seed0):
     return X, scales
 
 
-def measured_traffic(workload_tag):
+def measured_traffic(workload_tag, fold_cfg):
     """HBM bytes per fold launch from the committed rocprofv3 summary of this
-    workload, if the fold kernel source is unchanged since the counters were
-    taken (else None)."""
+    workload, if the fold kernel source and launch shape are those the
+    counters were taken with (else None)."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", f"fold_kernel_hbm_bytes_{workload_tag}.txt")
@@ -86,6 +91,9 @@ def measured_traffic(workload_tag):
     src = open(os.path.join(ROOT, "paper_2011_05698_amd", "csrc", "fold.hip"), "rb").read()
     if vals.get("fold_sha256_16") != hashlib.sha256(src).hexdigest()[:16]:
         return None, "fold kernel changed since the counters were taken"
+    shape = f"{fold_cfg['unroll']},{fold_cfg['wg_per_cu']}" if fold_cfg else None
+    if vals.get("fold_config") != shape:
+        return None, f"counters were taken with fold shape {vals.get('fold_config')}, this run uses {shape}"
     return int(float(vals["fold_hbm_bytes_per_launch"])), os.path.relpath(path, ROOT)
 
 
@@ -114,6 +122,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default fold launch shape")
+    ap.add_argument("--layout", default="position-major", choices=["position-major", "per-signal"],
+                    help="batch storage: sample c of signal s at X[c, s] (one plan), or one buffer per signal")
+    ap.add_argument("--no-context", action="store_true", help="skip timing the other layout")
+    ap.add_argument("--fold-config", default=None, metavar="U,CAP",
+                    help="fold launch shape (taps per thread, workgroups per CU cap) instead of tuning")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB a few times (scales HBM byte counters)")
     args = ap.parse_args()
@@ -155,64 +168,98 @@ def main():
 
     t0 = time.perf_counter()
     plan = sfft.Plan(N, K, B, w, M, l, q, delta=delta, seed=plan_seed, dtype=dt)
-    batch = sfft.Batch([plan] * n)
-    log(f"plan + batch built in {time.perf_counter() - t0:.1f}s (samples/signal {plan.samples})")
-    outs = batch.outputs(dev)
-    xs = [X[i] for i in range(n)]
+    log(f"plan built in {time.perf_counter() - t0:.1f}s (samples/signal {plan.samples})")
     stream = torch.cuda.current_stream()
-
-    batch.execute(xs, scales=scales, outs=outs)      # binds buffers, builds the graph
-    torch.cuda.synchronize()
-    fold_cfg = None
-    if not args.no_autotune:
-        t0 = time.perf_counter()
-        fold_cfg = batch.autotune()
-        log(f"fold autotune: {fold_cfg} in {time.perf_counter() - t0:.1f}s")
-        batch.execute(xs, scales=scales, outs=outs)  # re-captures with the chosen launch shape
+    XT = None
+    if args.layout == "position-major" or not args.no_context:
+        # sample c of signal s at XT[c, s]: one transpose of the batch (synthesis, untimed)
+        XT = X.transpose(0, 1).contiguous()
         torch.cuda.synchronize()
-    for _ in range(args.warmup):
-        batch.execute(xs, scales=scales, outs=outs)
-    torch.cuda.synchronize()
-    log(f"warmup done ({args.warmup} steps)")
 
-    # ---- timed region: K steps, stage by stage, events between stages ----
+    def run_layout(layout, steps):
+        """Bind, tune, warm up and time `steps` passes of the batch in one layout."""
+        if layout == "position-major":
+            batch = sfft.InterleavedBatch(plan, n)
+            outs = batch.outputs(dev)
+            run = lambda: batch.execute(XT, scales=scales, outs=outs)  # noqa: E731
+        else:
+            batch = sfft.Batch([plan] * n)
+            outs = batch.outputs(dev)
+            xs = [X[i] for i in range(n)]
+            run = lambda: batch.execute(xs, scales=scales, outs=outs)  # noqa: E731
+        run()  # binds buffers, builds the graph
+        torch.cuda.synchronize()
+        fold_cfg = None
+        if args.fold_config:
+            u, cap = (int(v) for v in args.fold_config.split(","))
+            cap = 0 if layout == "position-major" else cap
+            batch.set_fold_config(u, cap)
+            fold_cfg = {"unroll": u, "wg_per_cu": cap, "fold_ms": None}
+        elif not args.no_autotune:
+            t1 = time.perf_counter()
+            fold_cfg = batch.autotune()
+            log(f"[{layout}] fold autotune: {fold_cfg} in {time.perf_counter() - t1:.1f}s")
+        run()  # captures with the chosen launch shape
+        torch.cuda.synchronize()
+        for _ in range(args.warmup):
+            run()
+        torch.cuda.synchronize()
+        # timed region: stage by stage, events between stages
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for k in range(steps):
+            ev[k][0].record(stream)
+            batch.launch_stage(0)
+            ev[k][1].record(stream)
+            batch.launch_stage(1)
+            ev[k][2].record(stream)
+            batch.launch_stage(2)
+            ev[k][3].record(stream)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t1
+        stage_ms = [float(np.mean([ev[k][i].elapsed_time(ev[k][i + 1]) for k in range(steps)])) for i in range(3)]
+        # graph replay of the same work (the execute path)
+        torch.cuda.synchronize()
+        tg = time.perf_counter()
+        for _ in range(steps):
+            run()
+        torch.cuda.synchronize()
+        graph_ms = (time.perf_counter() - tg) * 1e3 / steps
+        res = {"layout": layout, "value": n * steps / elapsed, "ms_per_step": elapsed * 1e3 / steps,
+               "stage_ms": stage_ms, "graph_ms_per_step": graph_ms, "fold_cfg": fold_cfg, "outs": outs}
+        log(f"[{layout}] timed {steps} steps: {res['ms_per_step']:.3f} ms/step, {res['value']:.1f} signals/s; "
+            f"stages ms {[round(v, 4) for v in stage_ms]}; graph {graph_ms:.3f} ms/step")
+        batch.close()
+        return res
+
+    main_res = run_layout(args.layout, args.steps)
+    context = None
+    if not args.no_context:
+        other = "per-signal" if args.layout == "position-major" else "position-major"
+        r = run_layout(other, max(2, args.steps // 2))
+        context = {"layout": other, "signals_per_s": round(r["value"], 1), "ms_per_step": round(r["ms_per_step"], 4),
+                   "stage_ms": {"fold": round(r["stage_ms"][0], 4), "bucket_fft": round(r["stage_ms"][1], 4),
+                                "recover": round(r["stage_ms"][2], 4)},
+                   "fold_launch": r["fold_cfg"]}
     K_steps = args.steps
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(K_steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(K_steps):
-        ev[k][0].record(stream)
-        batch.launch_stage(0)
-        ev[k][1].record(stream)
-        batch.launch_stage(1)
-        ev[k][2].record(stream)
-        batch.launch_stage(2)
-        ev[k][3].record(stream)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    stage_ms = [float(np.mean([ev[k][s].elapsed_time(ev[k][s + 1]) for k in range(K_steps)])) for s in range(3)]
-    ms_per_step = elapsed * 1e3 / K_steps
-    value = n * K_steps / elapsed
-    log(f"timed {K_steps} steps: {ms_per_step:.3f} ms/step, {value:.1f} signals/s; stages ms {stage_ms}")
-
-    # graph replay of the same work (the sfft_execute_batch path)
-    torch.cuda.synchronize()
-    tg = time.perf_counter()
-    for _ in range(K_steps):
-        batch.execute(xs, scales=scales, outs=outs)
-    torch.cuda.synchronize()
-    graph_ms = (time.perf_counter() - tg) * 1e3 / K_steps
+    stage_ms, ms_per_step, value = main_res["stage_ms"], main_res["ms_per_step"], main_res["value"]
+    graph_ms, fold_cfg, outs = main_res["graph_ms_per_step"], main_res["fold_cfg"], main_res["outs"]
+    if XT is not None and args.layout != "position-major":
+        del XT
 
     # ---- roofline of the dominant kernel (the fold) ----
     bytes_per_sample = {"c64": 8, "f16x2": 4, "c128": 16}[dt]
     out_bytes = 16 if dt == "c128" else 8
     alg_bytes = n * (plan.samples * bytes_per_sample + plan.yhat_elems * out_bytes)
     achieved = alg_bytes / (stage_ms[0] * 1e-3) / 1e9
-    tag = f"metric_batch{n}_{dt}" if (N, K, B, M, args.snr) == (2 ** 22, 1000, 2048, 12, None) else None
-    traffic, source = measured_traffic(tag) if tag else (None, None)
+    lay = "posmajor" if args.layout == "position-major" else "persignal"
+    tag = f"metric_batch{n}_{dt}_{lay}" if (N, K, B, M, args.snr) == (2 ** 22, 1000, 2048, 12, None) else None
+    traffic, source = measured_traffic(tag, fold_cfg) if tag else (None, None)
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-                "kernel": "fold_kernel", "alg_bytes_per_launch": alg_bytes,
+                "kernel": "fold_interleaved_kernel" if args.layout == "position-major" else "fold_kernel",
+                "alg_bytes_per_launch": alg_bytes,
                 "avg_launch_ms": round(stage_ms[0], 5)}
     if traffic:
         roofline["traffic_gbs"] = round(traffic / (stage_ms[0] * 1e-3) / 1e9, 1)
@@ -278,12 +325,14 @@ def main():
                                f"l={l}, q={q}, delta={delta}, storage {dt}, "
                                f"{'noiseless' if args.snr is None else f'SNR {args.snr} dB'}",
                    "batch": n, "N": N, "K": K, "B": B, "w": w, "loops": M, "multiscale": l, "extension": q,
-                   "storage": dt, "snr_db": args.snr, "samples_per_signal": plan.samples},
+                   "storage": dt, "snr_db": args.snr, "samples_per_signal": plan.samples,
+                   "layout": args.layout, "plan": "one plan (one sigma/tau draw) for the whole batch"},
         "roofline": roofline, "cpu_baseline": cpu, "parity": parity, "dense_fft": dense,
         "stage_ms": {"fold": round(stage_ms[0], 4), "bucket_fft": round(stage_ms[1], 4),
                      "recover": round(stage_ms[2], 4)},
         "graph_ms_per_step": round(graph_ms, 4),
         "fold_launch": fold_cfg,
+        "other_layout": context,
     }
     print(json.dumps(line), flush=True)
 

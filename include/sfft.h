@@ -197,13 +197,40 @@ sfft_status sfft_execute_batch(sfft_batch_t b, const void* const* h_x, const flo
                                int64_t* const* h_idx, void* const* h_val, int64_t* d_count, void* stream);
 
 /*
+ * Position-major batches: nsig signals that share one plan (one draw of the
+ * permutations sigma_m and offsets tau0_m, Sec. 2.4 and 3.1, applied to
+ * every signal) and are stored sample-interleaved, as a multichannel stream
+ * is: sample c of signal s is element c * ld + s of d_x (ld >= nsig; an
+ * element is one sample of the plan's dtype).  Since every signal gathers
+ * the same positions, each tap reads a contiguous run of the row instead of
+ * one sample per cache line.  Results are those sfft_execute gives for each
+ * signal on its own with the same plan.
+ *
+ * sfft_batch_create_interleaved -- the plan must outlive the batch.
+ * sfft_execute_interleaved --
+ *   d_x      device array of N rows of ld elements;
+ *   h_scale  host array of nsig scales (F16X2_SCALED plans) or NULL;
+ *   d_idx    device int64 array [nsig][K], d_val device array [nsig][K] of
+ *            the output value type, d_count device int64 array [nsig].
+ * Binding, graph replay and stream ordering are those of sfft_execute_batch
+ * (a changed d_x, ld, scale or output pointer re-uploads the descriptor
+ * table with a blocking copy).  SFFT_ERR_PARAM for ld < nsig or ld >= 2^32;
+ * SFFT_ERR_STATE when a batch of the other kind is passed to either execute
+ * call.  sfft_batch_launch_stage, sfft_batch_set_fold_config (unroll only;
+ * wg_per_cu is ignored), sfft_batch_autotune and sfft_batch_destroy apply.
+ */
+sfft_status sfft_batch_create_interleaved(sfft_batch_t* out, sfft_plan_t plan, int32_t nsig);
+sfft_status sfft_execute_interleaved(sfft_batch_t b, const void* d_x, int64_t ld, const float* h_scale,
+                                     int64_t* d_idx, void* d_val, int64_t* d_count, void* stream);
+
+/*
  * sfft_batch_launch_stage -- enqueue one stage of the batch on `stream`, for
  * timing the stages separately (the sequence fold, bucket DFT, recover is
  * exactly what sfft_execute_batch replays):
  *   stage 0: permuted gather + window + fold (HashToBins, Eq. 7, 10, 11)
  *   stage 1: B-point DFT of every round (Eq. 12 with the 1/N factor)
  *   stage 2: recovery (subtraction .. top-K)
- * Uses the buffers bound by the last sfft_execute_batch (SFFT_ERR_STATE if
+ * Uses the buffers bound by the last execute of the batch (SFFT_ERR_STATE if
  * none).
  */
 sfft_status sfft_batch_launch_stage(sfft_batch_t b, int32_t stage, void* stream);

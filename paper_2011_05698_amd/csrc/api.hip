@@ -47,6 +47,8 @@ struct sfft_batch_s {
   hipGraphExec_t exec = nullptr;
   hipStream_t capture_stream = nullptr;
   FoldConfig fold{8, 0};
+  bool interleaved = false;         // one plan, position-major signals (sfft_batch_create_interleaved)
+  uint32_t ngroups = 0;             // interleaved: signal groups of kIlvSigs
 };
 
 namespace {
@@ -204,11 +206,20 @@ sfft_status run_hash(sfft_plan_t p, const SigArg& a, hipStream_t s) {
   return SFFT_OK;
 }
 
+int launch_batch_fold(const sfft_batch_s* b, const FoldConfig& cfg, hipStream_t s);
+
 SigArg table_arg(const sfft_batch_s* b) {
   SigArg a;
   std::memset(&a, 0, sizeof(a));
   a.table = b->d_sigs;
   return a;
+}
+
+int launch_batch_fold(const sfft_batch_s* b, const FoldConfig& cfg, hipStream_t s) {
+  if (b->interleaved)
+    return launch_fold_interleaved(b->dtype, b->kahan, cfg.unroll, b->d_sigs, uint32_t(b->plans.size()), b->d_tiles,
+                                   b->ntiles, s);
+  return launch_fold(b->dtype, b->kahan, cfg, table_arg(b), b->d_tiles, b->ntiles, s);
 }
 
 }  // namespace
@@ -362,7 +373,17 @@ sfft_status sfft_recover(sfft_plan_t p, const void* d_yhat, int64_t* d_idx, void
   return SFFT_OK;
 }
 
-sfft_status sfft_batch_create(sfft_batch_t* out, const sfft_plan_t* h_plans, int32_t n) {
+// Position-major fold tiles: (iteration, block of kIlvItems items, signal group).
+void interleaved_tiles(const HostPlan& hp, uint32_t ngroups, std::vector<FoldTile>& tiles) {
+  for (int m = 0; m < hp.loops; ++m) {
+    const IterDesc& d = hp.iters[m].d;
+    const uint32_t nitem = (d.R + 1) * d.B;  // a multiple of kIlvItems: B >= 16
+    for (uint32_t i0 = 0; i0 < nitem; i0 += kIlvItems)
+      for (uint32_t g = 0; g < ngroups; ++g) tiles.push_back(FoldTile{g, uint32_t(m), i0});
+  }
+}
+
+sfft_status create_batch(sfft_batch_t* out, const sfft_plan_t* h_plans, int32_t n, bool interleaved) {
   if (!out || !h_plans || n < 1) return fail(SFFT_ERR_PARAM, "need at least one plan");
   *out = nullptr;
   for (int32_t s = 0; s < n; ++s) {
@@ -377,6 +398,7 @@ sfft_status sfft_batch_create(sfft_batch_t* out, const sfft_plan_t* h_plans, int
   b->dtype = h_plans[0]->hp.dtype;
   b->kahan = h_plans[0]->hp.kahan;
   b->fold = h_plans[0]->fold;
+  b->interleaved = interleaved;
   std::vector<FoldTile> tiles;
   std::vector<RoundItem> items;
   uint64_t ws = 0;
@@ -386,6 +408,11 @@ sfft_status sfft_batch_create(sfft_batch_t* out, const sfft_plan_t* h_plans, int
     b->ws_off.push_back(ws);
     ws += align256(hp.desc.ws_bytes);
     b->max_B = std::max(b->max_B, max_B(hp));
+  }
+  if (interleaved) {
+    b->ngroups = uint32_t((n + kIlvSigs - 1) / kIlvSigs);
+    tiles.clear();
+    interleaved_tiles(h_plans[0]->hp, b->ngroups, tiles);
   }
   b->ntiles = uint32_t(tiles.size());
   b->nitems = uint32_t(items.size());
@@ -414,25 +441,14 @@ sfft_status sfft_batch_create(sfft_batch_t* out, const sfft_plan_t* h_plans, int
   return SFFT_OK;
 }
 
-sfft_status sfft_execute_batch(sfft_batch_t b, const void* const* h_x, const float* h_scale, int64_t* const* h_idx,
-                               void* const* h_val, int64_t* d_count, void* stream) {
-  if (!b || !h_x || !h_idx || !h_val || !d_count) return fail(SFFT_ERR_PARAM, "null argument");
-  const size_t n = b->plans.size();
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  std::vector<SignalDesc> sig(n);
-  for (size_t i = 0; i < n; ++i) {
-    if (!h_x[i] || !h_idx[i] || !h_val[i]) return fail(SFFT_ERR_PARAM, "null signal buffer");
-    sfft_plan_t p = b->plans[i];
-    SignalDesc& sd = sig[i];
-    sd.plan = p->d_plan;
-    sd.x = h_x[i];
-    sd.ws = b->d_ws + b->ws_off[i];
-    sd.y = b->d_ws + b->ws_off[i] + p->hp.desc.off_y;
-    sd.idx = h_idx[i];
-    sd.val = h_val[i];
-    sd.count = d_count + i;
-    sd.scale = h_scale ? h_scale[i] : 1.0f;
-  }
+sfft_status sfft_batch_create(sfft_batch_t* out, const sfft_plan_t* h_plans, int32_t n) {
+  return create_batch(out, h_plans, n, false);
+}
+
+// Uploads the descriptor table when the buffers changed, captures the three
+// stages into the batch graph when there is none, and replays it on `stream`.
+sfft_status bind_and_replay(sfft_batch_t b, const std::vector<SignalDesc>& sig, hipStream_t s) {
+  const size_t n = sig.size();
   const bool same = b->has_binding && std::memcmp(sig.data(), b->bound.data(), sizeof(SignalDesc) * n) == 0;
   if (!same) {
     // new buffers: wait for this batch's work in flight, then upload the table
@@ -447,7 +463,7 @@ sfft_status sfft_execute_batch(sfft_batch_t b, const void* const* h_x, const flo
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
     const SigArg a = table_arg(b);
-    int le = launch_fold(b->dtype, b->kahan, b->fold, a, b->d_tiles, b->ntiles, cs);
+    int le = launch_batch_fold(b, b->fold, cs);
     if (le == hipSuccess) le = launch_bucket_fft(b->dtype, a, b->d_items, b->nitems, b->max_B, cs);
     if (le == hipSuccess) le = launch_recover(b->dtype, a, uint32_t(n), cs);
     hipGraph_t g = nullptr;
@@ -466,14 +482,69 @@ sfft_status sfft_execute_batch(sfft_batch_t b, const void* const* h_x, const flo
   return SFFT_OK;
 }
 
+sfft_status sfft_execute_batch(sfft_batch_t b, const void* const* h_x, const float* h_scale, int64_t* const* h_idx,
+                               void* const* h_val, int64_t* d_count, void* stream) {
+  if (!b || !h_x || !h_idx || !h_val || !d_count) return fail(SFFT_ERR_PARAM, "null argument");
+  if (b->interleaved) return fail(SFFT_ERR_STATE, "position-major batch: use sfft_execute_interleaved");
+  const size_t n = b->plans.size();
+  std::vector<SignalDesc> sig(n);
+  for (size_t i = 0; i < n; ++i) {
+    if (!h_x[i] || !h_idx[i] || !h_val[i]) return fail(SFFT_ERR_PARAM, "null signal buffer");
+    sfft_plan_t p = b->plans[i];
+    SignalDesc& sd = sig[i];
+    sd.plan = p->d_plan;
+    sd.x = h_x[i];
+    sd.ws = b->d_ws + b->ws_off[i];
+    sd.y = b->d_ws + b->ws_off[i] + p->hp.desc.off_y;
+    sd.idx = h_idx[i];
+    sd.val = h_val[i];
+    sd.count = d_count + i;
+    sd.scale = h_scale ? h_scale[i] : 1.0f;
+    sd.ld = 0;
+  }
+  return bind_and_replay(b, sig, reinterpret_cast<hipStream_t>(stream));
+}
+
+sfft_status sfft_batch_create_interleaved(sfft_batch_t* out, sfft_plan_t plan, int32_t nsig) {
+  if (!out || nsig < 1) return fail(SFFT_ERR_PARAM, "need a plan and at least one signal");
+  std::vector<sfft_plan_t> plans(size_t(nsig), plan);
+  return create_batch(out, plans.data(), nsig, true);
+}
+
+sfft_status sfft_execute_interleaved(sfft_batch_t b, const void* d_x, int64_t ld, const float* h_scale,
+                                     int64_t* d_idx, void* d_val, int64_t* d_count, void* stream) {
+  if (!b || !d_x || !d_idx || !d_val || !d_count) return fail(SFFT_ERR_PARAM, "null argument");
+  if (!b->interleaved) return fail(SFFT_ERR_STATE, "not a position-major batch: use sfft_execute_batch");
+  const size_t n = b->plans.size();
+  if (ld < int64_t(n) || ld > int64_t(UINT32_MAX)) return fail(SFFT_ERR_PARAM, "ld must satisfy nsig <= ld < 2^32");
+  sfft_plan_t p = b->plans[0];
+  const uint64_t es = b->dtype == SFFT_C128 ? 16 : b->dtype == SFFT_F16X2_SCALED ? 4 : 8;  // input element
+  const uint64_t vs = b->dtype == SFFT_C128 ? 16 : 8;                                      // output value
+  const uint64_t K = p->hp.desc.K;
+  std::vector<SignalDesc> sig(n);
+  for (size_t i = 0; i < n; ++i) {
+    SignalDesc& sd = sig[i];
+    sd.plan = p->d_plan;
+    sd.x = reinterpret_cast<const unsigned char*>(d_x) + i * es;
+    sd.ws = b->d_ws + b->ws_off[i];
+    sd.y = b->d_ws + b->ws_off[i] + p->hp.desc.off_y;
+    sd.idx = d_idx + i * K;
+    sd.val = reinterpret_cast<unsigned char*>(d_val) + i * K * vs;
+    sd.count = d_count + i;
+    sd.scale = h_scale ? h_scale[i] : 1.0f;
+    sd.ld = uint32_t(ld);
+  }
+  return bind_and_replay(b, sig, reinterpret_cast<hipStream_t>(stream));
+}
+
 sfft_status sfft_batch_launch_stage(sfft_batch_t b, int32_t stage, void* stream) {
   if (!b) return fail(SFFT_ERR_PARAM, "null batch");
-  if (!b->has_binding) return fail(SFFT_ERR_STATE, "no buffers bound: call sfft_execute_batch first");
+  if (!b->has_binding) return fail(SFFT_ERR_STATE, "no buffers bound: execute the batch first");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   int e;
   const SigArg a = table_arg(b);
   switch (stage) {
-    case 0: e = launch_fold(b->dtype, b->kahan, b->fold, a, b->d_tiles, b->ntiles, s); break;
+    case 0: e = launch_batch_fold(b, b->fold, s); break;
     case 1: e = launch_bucket_fft(b->dtype, a, b->d_items, b->nitems, b->max_B, s); break;
     case 2: e = launch_recover(b->dtype, a, uint32_t(b->plans.size()), s); break;
     default: return fail(SFFT_ERR_PARAM, "stage must be 0, 1 or 2");
@@ -506,24 +577,24 @@ sfft_status sfft_batch_set_fold_config(sfft_batch_t b, const sfft_fold_config* c
 
 sfft_status sfft_batch_autotune(sfft_batch_t b, void* stream, sfft_fold_config* best) {
   if (!b) return fail(SFFT_ERR_PARAM, "null batch");
-  if (!b->has_binding) return fail(SFFT_ERR_STATE, "no buffers bound: call sfft_execute_batch first");
+  if (!b->has_binding) return fail(SFFT_ERR_STATE, "no buffers bound: execute the batch first");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const SigArg a = table_arg(b);
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return fail(SFFT_ERR_LAUNCH, "hipEventCreate");
   const int unrolls[3] = {8, 16, 24};
   const int caps[5] = {0, 2, 3, 4, 6};
+  const int ncaps = b->interleaved ? 1 : 5;  // the position-major fold has no residency cap
   FoldConfig win = b->fold;
   float win_ms = 1e30f;
   sfft_status st = SFFT_OK;
   for (int ui = 0; ui < 3 && st == SFFT_OK; ++ui) {
-    for (int ci = 0; ci < 5 && st == SFFT_OK; ++ci) {
+    for (int ci = 0; ci < ncaps && st == SFFT_OK; ++ci) {
       const FoldConfig c{unrolls[ui], caps[ci]};
-      int le = launch_fold(b->dtype, b->kahan, c, a, b->d_tiles, b->ntiles, s);  // warm
+      int le = launch_batch_fold(b, c, s);  // warm
       float total = 0.f;
       for (int r = 0; r < 3 && le == hipSuccess; ++r) {
         (void)hipEventRecord(e0, s);
-        le = launch_fold(b->dtype, b->kahan, c, a, b->d_tiles, b->ntiles, s);
+        le = launch_batch_fold(b, c, s);
         (void)hipEventRecord(e1, s);
         if (hipEventSynchronize(e1) != hipSuccess) le = hipErrorLaunchFailure;
         float ms = 0.f;

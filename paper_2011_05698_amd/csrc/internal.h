@@ -67,7 +67,7 @@ struct SignalDesc {
   void* val;
   int64_t* count;
   float scale;
-  uint32_t pad;
+  uint32_t ld;                     // position-major batches: elements between samples c and c+1 (0: contiguous)
 };
 
 // How the stage kernels receive signal descriptors: a batch table in device
@@ -133,8 +133,15 @@ struct FoldConfig {
   int wg_per_cu;    // 0: no cap; else 2..8
 };
 int fold_lds_bytes(int wg_per_cu);
+constexpr int kIlvItems = 16;      // (round, bucket) items per position-major fold workgroup
+constexpr int kIlvSigs = 64;       // signals per position-major fold workgroup, one per lane
 int launch_fold(int dtype, int kahan, const FoldConfig& cfg, const SigArg& sig, const FoldTile* d_tiles,
                 uint32_t ntiles, void* stream);
+// Position-major batch (one plan; sample c of signal s at table[s].x + c * ld,
+// with table[s].x = table[0].x + s): tiles of kIlvItems items x kIlvSigs
+// signals, FoldTile.sig = index of the signal group.
+int launch_fold_interleaved(int dtype, int kahan, int unroll, const SignalDesc* table, uint32_t nsig,
+                            const FoldTile* d_tiles, uint32_t ntiles, void* stream);
 int launch_bucket_fft(int dtype, const SigArg& sig, const RoundItem* d_items, uint32_t nitems, uint32_t max_B,
                       void* stream);
 int launch_recover(int dtype, const SigArg& sig, uint32_t nsig, void* stream);

@@ -19,6 +19,7 @@ constexpr int kWaves = kRecThreads / 64;
 constexpr int kLdsBytes = 32768;    // one buffer, reused phase by phase
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr int kRegRounds = 16;      // rounds whose estimates are sorted in registers
+constexpr int kSubRounds = 8;       // rounds accumulated together by the subtraction
 
 struct K128 {
   uint64_t hi, lo;
@@ -470,53 +471,79 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
     // ---- subtraction of the coefficients recovered so far ----
     // The store is sorted by its permuted frequency u = sigma f mod N, so the
     // coefficients that leak into bucket i (circular distance |iL - u| <= D)
-    // form one circular run of the sorted list.  Each (bucket, round) sum is
-    // split over a team of lanes sized to the mean run length and closed by
-    // a butterfly of fixed shape: the order of every sum depends only on the
-    // recovered set, not on how the store was filled.
+    // form one circular run of the sorted list.  A team of lanes, sized to
+    // the mean run length, takes one bucket at a time: one binary search, then
+    // each lane walks its share of the run and adds every entry to all rounds
+    // (up to kSubRounds accumulators), and a butterfly of fixed shape closes
+    // the sums.  The order of every sum depends only on the recovered set, not
+    // on how the store was filled.
     if (nrec > 0) {
       uint32_t npow = 1;
       while (npow < nrec) npow <<= 1;
-      uint64_t* sk = npow * 8u <= uint32_t(kLdsBytes) ? reinterpret_cast<uint64_t*>(lds_buf) : gkeys;
+      const bool keys_in_lds = npow * 8u <= uint32_t(kLdsBytes);
+      uint64_t* sk = keys_in_lds ? reinterpret_cast<uint64_t*>(lds_buf) : gkeys;
       for (uint32_t k = tid; k < npow; k += NT)
         sk[k] = k < nrec ? (uint64_t((sigma * rf[k]) & nmask) << 32) | k : ~uint64_t(0);
       __syncthreads();
       if (npow > 1) block_bitonic_sort(sk, npow);
+      // values in sorted order next to the keys when both fit
+      const uint32_t sv_off = (npow * 8u + 15u) & ~15u;  // complex128 values need 16-byte alignment
+      const bool vals_in_lds = keys_in_lds && sv_off + nrec * sizeof(cplx<R>) <= uint32_t(kLdsBytes);
+      cplx<R>* sv = reinterpret_cast<cplx<R>*>(lds_buf + sv_off);
+      if (vals_in_lds) {
+        for (uint32_t q = tid; q < nrec; q += NT) sv[q] = rv[uint32_t(sk[q])];
+        __syncthreads();
+      }
       // team size: smallest power of two >= the mean run length, in [1, 64]
       const double mean_run = double(nrec) * double(2 * D + 1) / double(N);
       uint32_t S = 1;
       while (S < 64 && double(S) < mean_run) S <<= 1;
       const uint32_t team = tid / S, lane = tid & (S - 1), nteams = NT / S;
-      const uint32_t nout = B * R1;
       const uint32_t span = 2 * D + 1;  // < N
-      for (uint32_t base = 0; base < nout; base += nteams) {  // uniform trip count per wave
-        const uint32_t o = base + team;
-        cplx<R> acc{0, 0};
-        if (o < nout) {
-          const uint32_t i = o / R1, j = o - i * R1;
-          const uint32_t a = (i * L - D) & nmask;  // first u of the run
-          const uint64_t stop = uint64_t(a) + span;
-          const uint32_t q0 = sorted_lower_bound(sk, nrec, a);
-          const uint32_t cnt = stop <= N ? sorted_lower_bound(sk, nrec, uint32_t(stop)) - q0
-                                         : nrec - q0 + sorted_lower_bound(sk, nrec, uint32_t(stop - N));
-          const uint32_t Tj = it->T[j];
-          for (uint32_t v = lane; v < cnt; v += S) {
-            uint32_t q = q0 + v;
-            q = q >= nrec ? q - nrec : q;
-            const uint64_t key = sk[q];
-            const uint32_t u = uint32_t(key >> 32), k = uint32_t(key);
-            const uint32_t d1 = (i * L - u) & nmask;
-            const cplx<R> vg = cscale(rv[k], ghat[min(d1, N - d1)]);
-            acc = cadd(acc, cmul(vg, expi<R>((Tj * u) & nmask, logN, R(-1))));
+      for (uint32_t j0 = 0; j0 < R1; j0 += kSubRounds) {
+        const uint32_t nj = min(R1 - j0, uint32_t(kSubRounds));
+        for (uint32_t base = 0; base < B; base += nteams) {  // uniform trip count per wave
+          const uint32_t i = base + team;
+          cplx<R> acc[kSubRounds];
+#pragma unroll
+          for (int jj = 0; jj < kSubRounds; ++jj) acc[jj] = cplx<R>{0, 0};
+          if (i < B) {
+            const uint32_t a = (i * L - D) & nmask;  // first u of the run
+            const uint64_t stop = uint64_t(a) + span;
+            const uint32_t q0 = sorted_lower_bound(sk, nrec, a);
+            const uint32_t cnt = stop <= N ? sorted_lower_bound(sk, nrec, uint32_t(stop)) - q0
+                                           : nrec - q0 + sorted_lower_bound(sk, nrec, uint32_t(stop - N));
+            for (uint32_t v = lane; v < cnt; v += S) {
+              uint32_t q = q0 + v;
+              q = q >= nrec ? q - nrec : q;
+              const uint64_t key = sk[q];
+              const uint32_t u = uint32_t(key >> 32);
+              const uint32_t d1 = (i * L - u) & nmask;
+              const cplx<R> rvq = vals_in_lds ? sv[q] : rv[uint32_t(key)];
+              const cplx<R> vg = cscale(rvq, ghat[min(d1, N - d1)]);
+#pragma unroll
+              for (int jj = 0; jj < kSubRounds; ++jj)
+                if (uint32_t(jj) < nj)
+                  acc[jj] = cadd(acc[jj], cmul(vg, expi<R>((it->T[j0 + jj] * u) & nmask, logN, R(-1))));
+            }
           }
-        }
-        for (uint32_t off = S >> 1; off > 0; off >>= 1) {
-          acc.re += __shfl_xor(acc.re, int(off), 64);
-          acc.im += __shfl_xor(acc.im, int(off), 64);
-        }
-        if (o < nout && lane == 0) {
-          const uint32_t i = o / R1, j = o - i * R1;
-          Y[size_t(j) * B + i] = csub(Y[size_t(j) * B + i], acc);
+#pragma unroll
+          for (int jj = 0; jj < kSubRounds; ++jj) {
+            if (uint32_t(jj) < nj) {  // nj is uniform
+              for (uint32_t off = S >> 1; off > 0; off >>= 1) {
+                acc[jj].re += __shfl_xor(acc[jj].re, int(off), 64);
+                acc[jj].im += __shfl_xor(acc[jj].im, int(off), 64);
+              }
+            }
+          }
+          if (i < B && lane == 0) {
+#pragma unroll
+            for (int jj = 0; jj < kSubRounds; ++jj)
+              if (uint32_t(jj) < nj) {
+                cplx<R>* yp = Y + size_t(j0 + jj) * B + i;
+                *yp = csub(*yp, acc[jj]);
+              }
+          }
         }
       }
       __syncthreads();

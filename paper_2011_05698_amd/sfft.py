@@ -27,7 +27,7 @@ EXPORTED = [
     "sfft_default_options", "sfft_plan", "sfft_execute", "sfft_hash_to_bins", "sfft_recover",
     "sfft_get_plan_info", "sfft_get_iter_info", "sfft_plan_dump_tables", "sfft_destroy",
     "sfft_batch_create", "sfft_execute_batch", "sfft_batch_launch_stage", "sfft_batch_destroy",
-    "sfft_plan_set_fold_config", "sfft_batch_set_fold_config", "sfft_batch_autotune", "sfft_status_string",
+    "sfft_batch_create_interleaved", "sfft_execute_interleaved", "sfft_plan_set_fold_config", "sfft_batch_set_fold_config", "sfft_batch_autotune", "sfft_status_string",
     "sfft_last_error",
 ]
 
@@ -109,6 +109,8 @@ def _load():
         "sfft_plan_set_fold_config": (i32, [vp, ctypes.POINTER(FoldConfig)]),
         "sfft_batch_set_fold_config": (i32, [vp, ctypes.POINTER(FoldConfig)]),
         "sfft_batch_autotune": (i32, [vp, vp, ctypes.POINTER(FoldConfig)]),
+        "sfft_batch_create_interleaved": (i32, [ctypes.POINTER(vp), vp, i32]),
+        "sfft_execute_interleaved": (i32, [vp, vp, i64, vp, vp, vp, vp, vp]),
         "sfft_batch_destroy": (i32, [vp]),
         "sfft_status_string": (ctypes.c_char_p, [i32]),
         "sfft_last_error": (ctypes.c_char_p, []),
@@ -203,6 +205,18 @@ def sfft_execute_batch(batch, xs, scales, idxs, vals, counts, stream=None):
     pv = (ctypes.c_void_p * n)(*[t.data_ptr() for t in vals])
     ps = None if scales is None else (ctypes.c_float * n)(*[float(s) for s in scales])
     _check(_lib.sfft_execute_batch(batch, px, ps, pi, pv, _ptr(counts), _stream(stream)))
+
+
+def sfft_batch_create_interleaved(plan, nsig):
+    h = ctypes.c_void_p()
+    _check(_lib.sfft_batch_create_interleaved(ctypes.byref(h), plan, nsig))
+    return h
+
+
+def sfft_execute_interleaved(batch, x, ld, scales, idx, val, counts, stream=None):
+    n = len(scales) if scales is not None else None
+    ps = None if scales is None else (ctypes.c_float * n)(*[float(s) for s in scales])
+    _check(_lib.sfft_execute_interleaved(batch, _ptr(x), ld, ps, _ptr(idx), _ptr(val), _ptr(counts), _stream(stream)))
 
 
 def sfft_batch_launch_stage(batch, stage, stream=None):
@@ -351,3 +365,36 @@ class Batch:
         idxs, vals, counts = outs
         sfft_execute_batch(self.handle, xs, scales, idxs, vals, counts, stream)
         return idxs, vals, counts
+
+
+class InterleavedBatch(Batch):
+    """nsig signals sharing one plan, stored position-major: x[c, s] is sample
+    c of signal s (a tensor of shape [N, ld] with ld >= nsig, or [N, ld, 2]
+    float16 for the F16X2 form; see sfft_batch_create_interleaved)."""
+
+    def __init__(self, plan, nsig):
+        self.plans = [plan] * nsig
+        self.plan = plan
+        self.nsig = nsig
+        self.handle = sfft_batch_create_interleaved(plan.handle, nsig)
+
+    def outputs(self, device):
+        import torch
+        vdt = torch.complex128 if self.plan.dtype == "c128" else torch.complex64
+        return (torch.zeros((self.nsig, self.plan.K), dtype=torch.int64, device=device),
+                torch.zeros((self.nsig, self.plan.K), dtype=vdt, device=device),
+                torch.zeros(self.nsig, dtype=torch.int64, device=device))
+
+    def execute(self, x, scales=None, outs=None, stream=None):
+        if outs is None:
+            outs = self.outputs(x.device)
+        pair = x.dim() == 3  # float16 (re, im) pairs
+        ok = x.shape[0] == self.plan.N and x.shape[1] >= self.nsig and (
+            (not pair and x.dim() == 2 and x.stride(1) == 1) or
+            (pair and x.shape[2] == 2 and x.stride(2) == 1 and x.stride(1) == 2 and x.stride(0) % 2 == 0))
+        if not ok:
+            raise ValueError("x must be [N, ld] (or [N, ld, 2] float16) with ld >= nsig, contiguous along signals")
+        idx, val, counts = outs
+        ld = x.stride(0) // 2 if pair else x.stride(0)
+        sfft_execute_interleaved(self.handle, x, ld, scales, idx, val, counts, stream)
+        return idx, val, counts

@@ -223,6 +223,90 @@ def test_batch_uneven_matches_single(sf):
         batch.set_fold_config(12, 0)
 
 
+def _position_major(xs_dev, ld, dtype):
+    """Stack device signals into the position-major layout [N, ld] (or
+    [N, ld, 2] float16 pairs); columns beyond the signals stay zero."""
+    N = xs_dev[0].shape[0]
+    if dtype == "f16x2":
+        X = torch.zeros((N, ld, 2), dtype=torch.float16, device=DEV)
+    else:
+        X = torch.zeros((N, ld), dtype=xs_dev[0].dtype, device=DEV)
+    for s, x in enumerate(xs_dev):
+        X[:, s] = x
+    return X
+
+
+@pytest.mark.parametrize("dtype,kahan,nsig,ld", [("c64", False, 70, 72), ("c128", True, 5, 5), ("f16x2", False, 66, 67)],
+                         ids=["c64_70sig_ragged", "c128_kahan_5sig", "f16x2_66sig"])
+def test_position_major_matches_single(sf, dtype, kahan, nsig, ld):
+    """A position-major batch (one plan, sample c of signal s at X[c, s]) gives
+    bit for bit what single executes of the same plan give, for a ragged
+    last signal group and every storage form; sampled signals match the
+    oracle."""
+    N, K, B, w, M = 2 ** 14, 40, 512, 7169, 8
+    plan = sf.Plan(N, K, B, w, M, 16, 1.0, delta=1e-6, seed=900, dtype=dtype, kahan=kahan)
+    xs, scales, xqs, singles = [], [], [], []
+    for s in range(nsig):
+        x, _, _ = make_signal(SignalSpec(N, 1 + (7 * s) % K, 1000 + s))
+        xd, scale, xq = to_dev(x, dtype)
+        xs.append(xd)
+        scales.append(scale)
+        xqs.append(xq)
+        singles.append(run_gpu(sf, plan, xd, scale))
+    X = _position_major(xs, ld, dtype)
+    batch = sf.InterleavedBatch(plan, nsig)
+    for unroll in (8, 24):
+        batch.set_fold_config(unroll, 0)
+        idx, val, cnt = batch.execute(X, scales=scales)
+        torch.cuda.synchronize()
+        for s in range(nsig):
+            c = int(cnt[s].item())
+            assert c == singles[s][2]
+            assert np.array_equal(idx[s, :c].cpu().numpy(), singles[s][0])
+            assert np.array_equal(val[s, :c].cpu().numpy(), singles[s][1])
+    for s in (0, nsig - 1):
+        oidx, oval, _ = O.sfft(xqs[s], O.make_plan(N, K, B, w, M, 16, 1, 1e-6, seed=900))
+        c = int(cnt[s].item())
+        assert np.array_equal(idx[s, :c].cpu().numpy(), oidx)
+        tol = 1e-10 if dtype == "c128" else 1e-4
+        assert rel_l2(val[s, :c].cpu().numpy().astype(np.complex128), oval) <= tol
+    with pytest.raises(sf.SfftError):
+        sf.sfft_execute_interleaved(batch.handle, X, nsig - 1, scales, idx, val, cnt)
+
+
+def test_position_major_metric_shape(sf):
+    """The metric workload's shape (N = 2^22, K = 1000, B = 2048, w = 45057,
+    12 iterations) in the position-major layout bench.py times, tuned: 64
+    signals equal their single executes bit for bit; two sampled signals
+    match the oracle element by element."""
+    N, K, B, w, M, l, q, delta = 2 ** 22, 1000, 2048, 45057, 12, 16, Fraction(1), 1e-6
+    nsig = 64
+    plan = sf.Plan(N, K, B, w, M, l, q, delta=delta, seed=602)
+    X = torch.zeros((N, nsig), dtype=torch.complex64, device=DEV)
+    xq = {}
+    for s in range(nsig):
+        x, _, _ = make_signal(SignalSpec(N, K, 601 + s))
+        X[:, s] = torch.from_numpy(x.astype(np.complex64)).to(DEV)
+        if s in (0, nsig - 1):
+            xq[s] = x.astype(np.complex64).astype(np.complex128)
+    batch = sf.InterleavedBatch(plan, nsig)
+    idx, val, cnt = batch.execute(X)
+    batch.autotune()
+    idx, val, cnt = batch.execute(X)
+    torch.cuda.synchronize()
+    for s in range(nsig):
+        gi, gv, c = run_gpu(sf, plan, X[:, s].contiguous(), 1.0)
+        assert int(cnt[s].item()) == c
+        assert np.array_equal(idx[s, :c].cpu().numpy(), gi)
+        assert np.array_equal(val[s, :c].cpu().numpy(), gv)
+    P = O.make_plan(N, K, B, w, M, l, q, delta, seed=602)
+    for s, x in xq.items():
+        oidx, oval, _ = O.sfft(x, P)
+        c = int(cnt[s].item())
+        assert np.array_equal(idx[s, :c].cpu().numpy(), oidx)
+        assert rel_l2(val[s, :c].cpu().numpy().astype(np.complex128), oval) <= 1e-4
+
+
 def test_edge_cases(sf):
     N, B = 2 ** 12, 64
     plan = sf.Plan(N, 3, B, (B * 12) | 1, 6, 16, 1.0, delta=1e-8, seed=4)
