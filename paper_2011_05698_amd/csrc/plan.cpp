@@ -272,7 +272,7 @@ void layout_workspace(HostPlan& hp) {
   pd.off_candu = take(uint64_t(pd.Bmax) * 4);
   pd.off_candd = take(uint64_t(pd.Bmax) * 4);
   pd.off_candv = take(uint64_t(pd.Bmax) * 2 * rs);
-  pd.off_keys = take(uint64_t(pd.sort_cap) * 16);
+  pd.off_keys = take(uint64_t(pd.sort_cap) * 24);  // cell ends + two key arrays, or top-K keys
   pd.off_p0 = take(uint64_t(pd.Bmax) * rs);
   pd.ws_bytes = off;
 }

@@ -50,18 +50,6 @@ __device__ void block_bitonic_sort(Key* keys, uint32_t n) {
   }
 }
 
-// Number of sorted keys (u << 32 | k) among the first n whose u is below x.
-__device__ __forceinline__ uint32_t sorted_lower_bound(const uint64_t* keys, uint32_t n, uint32_t x) {
-  const uint64_t t = uint64_t(x) << 32;
-  uint32_t lo = 0, hi = n;
-  while (lo < hi) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (keys[mid] < t) lo = mid + 1;
-    else hi = mid;
-  }
-  return lo;
-}
-
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
   const uint32_t lane = threadIdx.x & 63;
 #pragma unroll
@@ -471,25 +459,59 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
     // ---- subtraction of the coefficients recovered so far ----
     // The store is sorted by its permuted frequency u = sigma f mod N, so the
     // coefficients that leak into bucket i (circular distance |iL - u| <= D)
-    // form one circular run of the sorted list.  A team of lanes, sized to
-    // the mean run length, takes one bucket at a time: one binary search, then
-    // each lane walks its share of the run and adds every entry to all rounds
-    // (up to kSubRounds accumulators), and a butterfly of fixed shape closes
-    // the sums.  The order of every sum depends only on the recovered set, not
-    // on how the store was filled.
+    // form one circular run of the sorted list.  The sort is a counting sort
+    // on the top bits of u (about one entry per cell) followed by exact ranks
+    // inside each cell, and the cell starts locate any run in O(1).  A team
+    // of lanes, sized to the mean run length, takes one bucket at a time: each
+    // lane walks its share of the run and adds every entry to all rounds (up
+    // to kSubRounds accumulators), and a butterfly of fixed shape closes the
+    // sums.  The order of every sum depends only on the recovered set, not on
+    // how the store was filled.
     if (nrec > 0) {
-      uint32_t npow = 1;
-      while (npow < nrec) npow <<= 1;
-      const bool keys_in_lds = npow * 8u <= uint32_t(kLdsBytes);
-      uint64_t* sk = keys_in_lds ? reinterpret_cast<uint64_t*>(lds_buf) : gkeys;
-      for (uint32_t k = tid; k < npow; k += NT)
-        sk[k] = k < nrec ? (uint64_t((sigma * rf[k]) & nmask) << 32) | k : ~uint64_t(0);
+      uint32_t npow = 1, logc = 0;
+      while (npow < nrec) {
+        npow <<= 1;
+        ++logc;
+      }
+      const uint32_t cshift = logN - logc;  // npow <= rec_cap < N
+      const uint32_t o_sk = (npow * 4u + 15u) & ~15u;
+      const uint32_t o_tmp = (o_sk + nrec * 8u + 15u) & ~15u;  // 16-byte aligned: complex128 values reuse it
+      const bool in_lds = o_tmp + nrec * 8u <= uint32_t(kLdsBytes);
+      unsigned char* base = in_lds ? lds_buf : reinterpret_cast<unsigned char*>(gkeys);
+      uint32_t* cend = reinterpret_cast<uint32_t*>(base);  // cell counts, then cell ends
+      uint64_t* sk = reinterpret_cast<uint64_t*>(base + o_sk);
+      uint64_t* tmp = reinterpret_cast<uint64_t*>(base + o_tmp);
+      for (uint32_t c = tid; c < npow; c += NT) cend[c] = 0;
       __syncthreads();
-      if (npow > 1) block_bitonic_sort(sk, npow);
-      // values in sorted order next to the keys when both fit
-      const uint32_t sv_off = (npow * 8u + 15u) & ~15u;  // complex128 values need 16-byte alignment
-      const bool vals_in_lds = keys_in_lds && sv_off + nrec * sizeof(cplx<R>) <= uint32_t(kLdsBytes);
-      cplx<R>* sv = reinterpret_cast<cplx<R>*>(lds_buf + sv_off);
+      for (uint32_t k = tid; k < nrec; k += NT) atomicAdd(&cend[((sigma * rf[k]) & nmask) >> cshift], 1u);
+      __syncthreads();
+      block_scan_array(cend, npow, wsum);  // cend[c] = start of cell c
+      for (uint32_t k = tid; k < nrec; k += NT) {
+        const uint32_t u = (sigma * rf[k]) & nmask;
+        tmp[atomicAdd(&cend[u >> cshift], 1u)] = (uint64_t(u) << 32) | k;  // cend[c] ends as the end of cell c
+      }
+      __syncthreads();
+      for (uint32_t p = tid; p < nrec; p += NT) {  // exact rank inside the cell
+        const uint64_t key = tmp[p];
+        const uint32_t c = uint32_t(key >> 32) >> cshift;
+        const uint32_t c0 = c ? cend[c - 1] : 0u, c1 = cend[c];
+        uint32_t r = 0;
+        for (uint32_t p2 = c0; p2 < c1; ++p2) r += tmp[p2] < key ? 1u : 0u;
+        sk[c0 + r] = key;
+      }
+      __syncthreads();
+      // number of sorted entries whose u is below x (x <= N)
+      auto lower = [&](uint32_t x) -> uint32_t {
+        if (x >= N) return nrec;
+        const uint32_t c = x >> cshift;
+        uint32_t q = c ? cend[c - 1] : 0u;
+        const uint32_t c1 = cend[c];
+        while (q < c1 && uint32_t(sk[q] >> 32) < x) ++q;
+        return q;
+      };
+      // values in sorted order (over the scattered copy, which is no longer needed)
+      const bool vals_in_lds = in_lds && o_tmp + nrec * sizeof(cplx<R>) <= uint32_t(kLdsBytes);
+      cplx<R>* sv = reinterpret_cast<cplx<R>*>(lds_buf + o_tmp);
       if (vals_in_lds) {
         for (uint32_t q = tid; q < nrec; q += NT) sv[q] = rv[uint32_t(sk[q])];
         __syncthreads();
@@ -510,9 +532,8 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
           if (i < B) {
             const uint32_t a = (i * L - D) & nmask;  // first u of the run
             const uint64_t stop = uint64_t(a) + span;
-            const uint32_t q0 = sorted_lower_bound(sk, nrec, a);
-            const uint32_t cnt = stop <= N ? sorted_lower_bound(sk, nrec, uint32_t(stop)) - q0
-                                           : nrec - q0 + sorted_lower_bound(sk, nrec, uint32_t(stop - N));
+            const uint32_t q0 = lower(a);
+            const uint32_t cnt = stop <= N ? lower(uint32_t(stop)) - q0 : nrec - q0 + lower(uint32_t(stop - N));
             for (uint32_t v = lane; v < cnt; v += S) {
               uint32_t q = q0 + v;
               q = q >= nrec ? q - nrec : q;
