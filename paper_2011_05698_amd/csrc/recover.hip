@@ -16,10 +16,11 @@ namespace sfft {
 
 constexpr int kRecThreads = 256;    // 4 waves; the radix select assumes >= 256
 constexpr int kWaves = kRecThreads / 64;
-constexpr int kLdsBytes = 32768;    // one buffer, reused phase by phase
+constexpr int kLdsBytes = 49152;    // one buffer, reused phase by phase
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr int kRegRounds = 16;      // rounds whose estimates are sorted in registers
 constexpr int kSubRounds = 8;       // rounds accumulated together by the subtraction
+constexpr int kVgBatch = 4;         // entries whose loads a thread issues together
 
 struct K128 {
   uint64_t hi, lo;
@@ -509,11 +510,44 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
         while (q < c1 && uint32_t(sk[q] >> 32) < x) ++q;
         return q;
       };
-      // values in sorted order (over the scattered copy, which is no longer needed)
-      const bool vals_in_lds = in_lds && o_tmp + nrec * sizeof(cplx<R>) <= uint32_t(kLdsBytes);
-      cplx<R>* sv = reinterpret_cast<cplx<R>*>(lds_buf + o_tmp);
-      if (vals_in_lds) {
-        for (uint32_t q = tid; q < nrec; q += NT) sv[q] = rv[uint32_t(sk[q])];
+      // v * Ghat of every entry for each bucket it reaches (slot r: bucket
+      // i0(u) + r, i0 = ceil((u - D) / L)), over the scattered copy, which is
+      // no longer needed.  A thread issues the loads of kVgBatch entries
+      // together, so the team loop below reads LDS only.
+      const uint32_t nslot = it->reach + 1;
+      const bool vg_in_lds = in_lds && nslot <= 3 && o_tmp + nrec * nslot * sizeof(cplx<R>) <= uint32_t(kLdsBytes);
+      cplx<R>* vgs = reinterpret_cast<cplx<R>*>(lds_buf + o_tmp);
+      if (vg_in_lds) {
+        for (uint32_t qb = 0; qb < nrec; qb += kVgBatch * NT) {
+          uint64_t key[kVgBatch];
+          cplx<R> val[kVgBatch];
+#pragma unroll
+          for (int e = 0; e < kVgBatch; ++e) {
+            const uint32_t q = qb + uint32_t(e) * NT + tid;
+            key[e] = q < nrec ? sk[q] : 0;
+          }
+#pragma unroll
+          for (int e = 0; e < kVgBatch; ++e) {
+            const uint32_t q = qb + uint32_t(e) * NT + tid;
+            val[e] = q < nrec ? rv[uint32_t(key[e])] : cplx<R>{0, 0};
+          }
+#pragma unroll
+          for (int e = 0; e < kVgBatch; ++e) {
+            const uint32_t q = qb + uint32_t(e) * NT + tid;
+            if (q < nrec) {
+              const int64_t u = int64_t(key[e] >> 32);
+              const int64_t i0 = -floor_div(int64_t(D) - u, int64_t(L));
+#pragma unroll
+              for (uint32_t r = 0; r < 3; ++r) {
+                if (r < nslot) {
+                  const int64_t dist = (i0 + int64_t(r)) * int64_t(L) - u;
+                  const int64_t ad = dist < 0 ? -dist : dist;
+                  vgs[q * nslot + r] = ad <= int64_t(D) ? cscale(val[e], ghat[ad]) : cplx<R>{0, 0};
+                }
+              }
+            }
+          }
+        }
         __syncthreads();
       }
       // team size: smallest power of two >= the mean run length, in [1, 64]
@@ -529,6 +563,12 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
           cplx<R> acc[kSubRounds];
 #pragma unroll
           for (int jj = 0; jj < kSubRounds; ++jj) acc[jj] = cplx<R>{0, 0};
+          cplx<R> yv[kSubRounds];  // this bucket's values, fetched before the sums
+          if (i < B && lane == 0) {
+#pragma unroll
+            for (int jj = 0; jj < kSubRounds; ++jj)
+              if (uint32_t(jj) < nj) yv[jj] = Y[size_t(j0 + jj) * B + i];
+          }
           if (i < B) {
             const uint32_t a = (i * L - D) & nmask;  // first u of the run
             const uint64_t stop = uint64_t(a) + span;
@@ -539,9 +579,14 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
               q = q >= nrec ? q - nrec : q;
               const uint64_t key = sk[q];
               const uint32_t u = uint32_t(key >> 32);
-              const uint32_t d1 = (i * L - u) & nmask;
-              const cplx<R> rvq = vals_in_lds ? sv[q] : rv[uint32_t(key)];
-              const cplx<R> vg = cscale(rvq, ghat[min(d1, N - d1)]);
+              cplx<R> vg;
+              if (vg_in_lds) {
+                const int64_t i0 = -floor_div(int64_t(D) - int64_t(u), int64_t(L));
+                vg = vgs[q * nslot + ((i - uint32_t(i0)) & (B - 1))];
+              } else {
+                const uint32_t d1 = (i * L - u) & nmask;
+                vg = cscale(rv[uint32_t(key)], ghat[min(d1, N - d1)]);
+              }
 #pragma unroll
               for (int jj = 0; jj < kSubRounds; ++jj)
                 if (uint32_t(jj) < nj)
@@ -560,10 +605,7 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
           if (i < B && lane == 0) {
 #pragma unroll
             for (int jj = 0; jj < kSubRounds; ++jj)
-              if (uint32_t(jj) < nj) {
-                cplx<R>* yp = Y + size_t(j0 + jj) * B + i;
-                *yp = csub(*yp, acc[jj]);
-              }
+              if (uint32_t(jj) < nj) Y[size_t(j0 + jj) * B + i] = csub(yv[jj], acc[jj]);
           }
         }
       }
