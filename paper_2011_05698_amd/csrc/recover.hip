@@ -16,7 +16,7 @@ namespace sfft {
 
 constexpr int kRecThreads = 256;    // 4 waves; the radix select assumes >= 256
 constexpr int kWaves = kRecThreads / 64;
-constexpr int kLdsBytes = 49152;    // one buffer, reused phase by phase
+constexpr int kLdsBytes = 75776;    // one buffer, reused phase by phase; two workgroups still fit a CU
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr int kRegRounds = 16;      // rounds whose estimates are sorted in registers
 constexpr int kSubRounds = 8;       // rounds accumulated together by the subtraction
@@ -422,9 +422,7 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
   __shared__ uint32_t nrec_sh;
   __shared__ R sh_red[kWaves];
   __shared__ uint64_t sh_u64[kWaves];
-  uint32_t* lds32 = reinterpret_cast<uint32_t*>(lds_buf);
   using RK = RealKey<R>;
-  typename RK::T* ldskey = reinterpret_cast<typename RK::T*>(lds_buf);
 
   const uint32_t tid = threadIdx.x, NT = blockDim.x;
   const SignalDesc sd = load_signal(arg, blockIdx.x);
@@ -435,11 +433,11 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
   cplx<R>* rv = reinterpret_cast<cplx<R>*>(ws + pd->off_recv);
   uint32_t* hk = reinterpret_cast<uint32_t*>(ws + pd->off_htkey);
   uint32_t* hi = reinterpret_cast<uint32_t*>(ws + pd->off_htidx);
-  uint32_t* cand_u = reinterpret_cast<uint32_t*>(ws + pd->off_candu);
-  uint32_t* cand_d = reinterpret_cast<uint32_t*>(ws + pd->off_candd);
-  cplx<R>* cand_v = reinterpret_cast<cplx<R>*>(ws + pd->off_candv);
+  uint32_t* g_cand_u = reinterpret_cast<uint32_t*>(ws + pd->off_candu);
+  uint32_t* g_cand_d = reinterpret_cast<uint32_t*>(ws + pd->off_candd);
+  cplx<R>* g_cand_v = reinterpret_cast<cplx<R>*>(ws + pd->off_candv);
   uint64_t* gkeys = reinterpret_cast<uint64_t*>(ws + pd->off_keys);
-  R* p0 = reinterpret_cast<R*>(ws + pd->off_p0);
+  R* g_p0 = reinterpret_cast<R*>(ws + pd->off_p0);
   const uint32_t N = pd->N, nmask = N - 1, logN = pd->logN, logh = pd->log_hcap;
   const uint32_t hmask = (1u << logh) - 1;
 
@@ -453,9 +451,48 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
   for (uint32_t m = 0; m < pd->M; ++m) {
     const IterDesc* it = pd->iters + m;
     const uint32_t B = it->B, L = it->L, D = it->D, R1 = it->R + 1;
-    cplx<R>* Y = Yall + it->y_off;
     const R* ghat = reinterpret_cast<const R*>(pd->ghat) + it->ghat_off;
     const uint32_t sigma = it->sigma;
+
+    // ---- LDS plan of the iteration ----
+    // The iteration's bucket block ((R+1) x B values) and the per-bucket
+    // arrays are staged in LDS when they fit beside the scratch that the
+    // subtraction and the detection need; otherwise they stay in the
+    // workspace.  The subtraction then updates the staged block in place and
+    // every later phase reads it from LDS.
+    uint32_t npow = 1, logc = 0;
+    while (npow < nrec) {
+      npow <<= 1;
+      ++logc;
+    }
+    const uint32_t nslot = it->reach + 1;  // buckets a coefficient can reach
+    const uint32_t o_sk = (npow * 4u + 15u) & ~15u;
+    const uint32_t o_tmp = (o_sk + nrec * 8u + 15u) & ~15u;
+    const uint32_t vg_bytes = nrec * nslot * uint32_t(sizeof(cplx<R>));
+    const uint32_t sub_need = nrec == 0 ? 0u : o_tmp + (nslot <= 3 && vg_bytes > nrec * 8u ? vg_bytes : nrec * 8u);
+    const uint32_t det_need = B * uint32_t(sizeof(typename RK::T));
+    const uint32_t scr_need = sub_need > det_need ? sub_need : det_need;
+    const uint32_t ys_bytes = (R1 * B * uint32_t(sizeof(cplx<R>)) + 15u) & ~15u;
+    const uint32_t pb_bytes = ((B * uint32_t(sizeof(R)) + 15u) & ~15u) + 2u * ((B * 4u + 15u) & ~15u) +
+                              B * uint32_t(sizeof(cplx<R>));
+    const bool y_lds = ys_bytes + scr_need <= uint32_t(kLdsBytes);
+    const uint32_t pb_at = y_lds ? ys_bytes : 0u;
+    const bool pb_lds = pb_at + pb_bytes + scr_need <= uint32_t(kLdsBytes);
+    const uint32_t scr_at = (pb_at + (pb_lds ? pb_bytes : 0u) + 15u) & ~15u;
+    unsigned char* scr = lds_buf + scr_at;
+    const uint32_t scr_bytes = uint32_t(kLdsBytes) - scr_at;
+    cplx<R>* const Yg = Yall + it->y_off;
+    cplx<R>* const Y = y_lds ? reinterpret_cast<cplx<R>*>(lds_buf) : Yg;
+    R* const p0 = pb_lds ? reinterpret_cast<R*>(lds_buf + pb_at) : g_p0;
+    uint32_t* const cand_u = pb_lds ? reinterpret_cast<uint32_t*>(lds_buf + pb_at + ((B * uint32_t(sizeof(R)) + 15u) & ~15u))
+                                    : g_cand_u;
+    uint32_t* const cand_d = pb_lds ? cand_u + ((B + 3u) & ~3u) : g_cand_d;
+    cplx<R>* const cand_v = pb_lds ? reinterpret_cast<cplx<R>*>(cand_d + ((B + 3u) & ~3u)) : g_cand_v;
+    typename RK::T* const ldskey = reinterpret_cast<typename RK::T*>(scr);
+    if (y_lds) {
+      for (uint32_t e = tid; e < R1 * B; e += NT) Y[e] = Yg[e];
+      __syncthreads();
+    }
 
     // ---- subtraction of the coefficients recovered so far ----
     // The store is sorted by its permuted frequency u = sigma f mod N, so the
@@ -469,16 +506,10 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
     // sums.  The order of every sum depends only on the recovered set, not on
     // how the store was filled.
     if (nrec > 0) {
-      uint32_t npow = 1, logc = 0;
-      while (npow < nrec) {
-        npow <<= 1;
-        ++logc;
-      }
       const uint32_t cshift = logN - logc;  // npow <= rec_cap < N
-      const uint32_t o_sk = (npow * 4u + 15u) & ~15u;
-      const uint32_t o_tmp = (o_sk + nrec * 8u + 15u) & ~15u;  // 16-byte aligned: complex128 values reuse it
-      const bool in_lds = o_tmp + nrec * 8u <= uint32_t(kLdsBytes);
-      unsigned char* base = in_lds ? lds_buf : reinterpret_cast<unsigned char*>(gkeys);
+      // o_tmp is 16-byte aligned: complex128 weights reuse that region
+      const bool in_lds = o_tmp + nrec * 8u <= scr_bytes;
+      unsigned char* base = in_lds ? scr : reinterpret_cast<unsigned char*>(gkeys);
       uint32_t* cend = reinterpret_cast<uint32_t*>(base);  // cell counts, then cell ends
       uint64_t* sk = reinterpret_cast<uint64_t*>(base + o_sk);
       uint64_t* tmp = reinterpret_cast<uint64_t*>(base + o_tmp);
@@ -514,9 +545,8 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
       // i0(u) + r, i0 = ceil((u - D) / L)), over the scattered copy, which is
       // no longer needed.  A thread issues the loads of kVgBatch entries
       // together, so the team loop below reads LDS only.
-      const uint32_t nslot = it->reach + 1;
-      const bool vg_in_lds = in_lds && nslot <= 3 && o_tmp + nrec * nslot * sizeof(cplx<R>) <= uint32_t(kLdsBytes);
-      cplx<R>* vgs = reinterpret_cast<cplx<R>*>(lds_buf + o_tmp);
+      const bool vg_in_lds = in_lds && nslot <= 3 && o_tmp + vg_bytes <= scr_bytes;
+      cplx<R>* vgs = reinterpret_cast<cplx<R>*>(scr + o_tmp);
       if (vg_in_lds) {
         for (uint32_t qb = 0; qb < nrec; qb += kVgBatch * NT) {
           uint64_t key[kVgBatch];
