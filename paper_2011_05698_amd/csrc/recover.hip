@@ -164,8 +164,17 @@ __device__ K block_select(const K* keys, uint32_t n, uint32_t k, uint32_t* hist,
   return prefix;
 }
 
-__device__ __forceinline__ int64_t floor_div(int64_t a, int64_t b) {  // b > 0
-  return a >= 0 ? a / b : -((-a + b - 1) / b);
+// Block-wide copy of a descriptor (a multiple of 4 bytes) into LDS.
+__device__ __forceinline__ void copy_words(void* dst, const void* src, size_t bytes) {
+  for (uint32_t w = threadIdx.x; w < bytes / 4; w += blockDim.x)
+    reinterpret_cast<uint32_t*>(dst)[w] = reinterpret_cast<const uint32_t*>(src)[w];
+}
+
+// First bucket i0 = ceil((u - D) / L) whose centre i0 L is within D of u
+// (possibly -1; taken mod B by the caller).  L is a power of two, so the
+// floor of the signed quotient is an arithmetic shift.
+__device__ __forceinline__ int64_t first_bucket(uint32_t u, uint32_t D, uint32_t logL) {
+  return -((int64_t(D) - int64_t(u)) >> logL);
 }
 
 // Hash index of the recovered store: frequency -> entry, linear probing.
@@ -422,11 +431,16 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
   __shared__ uint32_t nrec_sh;
   __shared__ R sh_red[kWaves];
   __shared__ uint64_t sh_u64[kWaves];
+  // the plan and the current iteration's descriptors, read in every phase
+  __shared__ PlanDesc sh_pd;
+  __shared__ IterDesc sh_it;
   using RK = RealKey<R>;
 
   const uint32_t tid = threadIdx.x, NT = blockDim.x;
   const SignalDesc sd = load_signal(arg, blockIdx.x);
-  const PlanDesc* pd = sd.plan;
+  copy_words(&sh_pd, sd.plan, sizeof(PlanDesc));
+  __syncthreads();
+  const PlanDesc* pd = &sh_pd;
   unsigned char* ws = reinterpret_cast<unsigned char*>(sd.ws);
   cplx<R>* Yall = reinterpret_cast<cplx<R>*>(sd.y);
   uint32_t* rf = reinterpret_cast<uint32_t*>(ws + pd->off_recf);
@@ -449,7 +463,9 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
   uint32_t nrec = 0;
 
   for (uint32_t m = 0; m < pd->M; ++m) {
-    const IterDesc* it = pd->iters + m;
+    copy_words(&sh_it, pd->iters + m, sizeof(IterDesc));
+    __syncthreads();
+    const IterDesc* it = &sh_it;
     const uint32_t B = it->B, L = it->L, D = it->D, R1 = it->R + 1;
     const R* ghat = reinterpret_cast<const R*>(pd->ghat) + it->ghat_off;
     const uint32_t sigma = it->sigma;
@@ -566,7 +582,7 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
             const uint32_t q = qb + uint32_t(e) * NT + tid;
             if (q < nrec) {
               const int64_t u = int64_t(key[e] >> 32);
-              const int64_t i0 = -floor_div(int64_t(D) - u, int64_t(L));
+              const int64_t i0 = first_bucket(uint32_t(u), D, it->logL);
 #pragma unroll
               for (uint32_t r = 0; r < 3; ++r) {
                 if (r < nslot) {
@@ -611,7 +627,7 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
               const uint32_t u = uint32_t(key >> 32);
               cplx<R> vg;
               if (vg_in_lds) {
-                const int64_t i0 = -floor_div(int64_t(D) - int64_t(u), int64_t(L));
+                const int64_t i0 = first_bucket(u, D, it->logL);
                 vg = vgs[q * nslot + ((i - uint32_t(i0)) & (B - 1))];
               } else {
                 const uint32_t d1 = (i * L - u) & nmask;
