@@ -51,14 +51,82 @@ __device__ void block_bitonic_sort(Key* keys, uint32_t n) {
   }
 }
 
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
-  const uint32_t lane = threadIdx.x & 63;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const uint32_t t = __shfl_up(v, off, 64);
-    if (lane >= uint32_t(off)) v += t;
+// ---- cross-lane moves within a wavefront (DPP) ----
+// dpp_move<CTRL, ROW_MASK, BANK_MASK>(old, v) returns v of the lane that CTRL
+// selects, 0 where that lane is outside the row, and `old` in rows or banks
+// masked off.  No LDS traffic and no waits: a fixed sequence of these gives
+// reductions and scans whose order of operations is fixed.
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
+constexpr int kDppShr1 = 0x111, kDppShr2 = 0x112, kDppShr3 = 0x113, kDppShr4 = 0x114, kDppShr8 = 0x118;
+constexpr int kDppMirror = 0x140;     // lane 15 - i of the row
+constexpr int kDppHalfMirror = 0x141; // lane 7 - i of the half row
+constexpr int kDppBcast15 = 0x142;    // lane 15 of the previous row
+constexpr int kDppBcast31 = 0x143;    // lane 31
+
+template <int CTRL, int RM = 0xF, int BM = 0xF, typename T>
+__device__ __forceinline__ T dpp_move(T old, T v) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit values");
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old), __builtin_bit_cast(int, v),
+                                                              CTRL, RM, BM, true));
+  } else {
+    const uint64_t o = __builtin_bit_cast(uint64_t, old), x = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = uint32_t(__builtin_amdgcn_update_dpp(int(uint32_t(o)), int(uint32_t(x)), CTRL, RM, BM, true));
+    const uint32_t hi =
+        uint32_t(__builtin_amdgcn_update_dpp(int(uint32_t(o >> 32)), int(uint32_t(x >> 32)), CTRL, RM, BM, true));
+    return __builtin_bit_cast(T, (uint64_t(hi) << 32) | lo);
   }
+}
+
+// Sum over aligned teams of S lanes (S a power of two <= 64, uniform).  The
+// team's sum is in its last lane (in every lane of the team for S <= 16).
+template <typename T>
+__device__ __forceinline__ T team_sum(T v, uint32_t S) {
+  if (S >= 2) v = v + dpp_move<kDppXor1>(T(0), v);
+  if (S >= 4) v = v + dpp_move<kDppXor2>(T(0), v);
+  if (S >= 8) v = v + dpp_move<kDppHalfMirror>(T(0), v);
+  if (S >= 16) v = v + dpp_move<kDppMirror>(T(0), v);
+  if (S >= 32) v = v + dpp_move<kDppBcast15, 0xA>(T(0), v);
+  if (S >= 64) v = v + dpp_move<kDppBcast31, 0xC>(T(0), v);
   return v;
+}
+
+// Max / min over the wavefront; the result is in lane 63.
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+  T o;
+  o = dpp_move<kDppXor1>(v, v); v = o > v ? o : v;
+  o = dpp_move<kDppXor2>(v, v); v = o > v ? o : v;
+  o = dpp_move<kDppHalfMirror>(v, v); v = o > v ? o : v;
+  o = dpp_move<kDppMirror>(v, v); v = o > v ? o : v;
+  o = dpp_move<kDppBcast15, 0xA>(v, v); v = o > v ? o : v;
+  o = dpp_move<kDppBcast31, 0xC>(v, v); v = o > v ? o : v;
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_min(T v) {
+  T o;
+  o = dpp_move<kDppXor1>(v, v); v = o < v ? o : v;
+  o = dpp_move<kDppXor2>(v, v); v = o < v ? o : v;
+  o = dpp_move<kDppHalfMirror>(v, v); v = o < v ? o : v;
+  o = dpp_move<kDppMirror>(v, v); v = o < v ? o : v;
+  o = dpp_move<kDppBcast15, 0xA>(v, v); v = o < v ? o : v;
+  o = dpp_move<kDppBcast31, 0xC>(v, v); v = o < v ? o : v;
+  return v;
+}
+
+// Inclusive prefix sum over the wavefront: row-local prefix from shifts by
+// 1, 2, 3, then 4 and 8, then the row totals through lanes 15 and 31.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  uint32_t s = v + dpp_move<kDppShr1>(0u, v);
+  s = s + dpp_move<kDppShr2>(0u, v);
+  s = s + dpp_move<kDppShr3>(0u, v);
+  s = s + dpp_move<kDppShr4, 0xF, 0xE>(0u, s);
+  s = s + dpp_move<kDppShr8, 0xF, 0xC>(0u, s);
+  s = s + dpp_move<kDppBcast15, 0xA>(0u, s);
+  s = s + dpp_move<kDppBcast31, 0xC>(0u, s);
+  return s;
 }
 
 // Exclusive prefix of one value per thread across the block; *total gets the sum.
@@ -97,11 +165,8 @@ __device__ uint32_t block_scan_array(uint32_t* a, uint32_t n, uint32_t* wsum) {
 
 template <typename V>
 __device__ V block_max(V v, V* sh) {
-  for (int off = 32; off > 0; off >>= 1) {
-    const V o = __shfl_xor(v, off, 64);
-    v = v > o ? v : o;
-  }
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  v = wave_max(v);
+  if ((threadIdx.x & 63) == 63) sh[threadIdx.x >> 6] = v;
   __syncthreads();
   V r = sh[0];
   for (uint32_t w = 1; w < blockDim.x / 64; ++w) r = r > sh[w] ? r : sh[w];
@@ -111,11 +176,8 @@ __device__ V block_max(V v, V* sh) {
 
 template <typename V>
 __device__ V block_min(V v, V* sh) {
-  for (int off = 32; off > 0; off >>= 1) {
-    const V o = __shfl_xor(v, off, 64);
-    v = o < v ? o : v;
-  }
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  v = wave_min(v);
+  if ((threadIdx.x & 63) == 63) sh[threadIdx.x >> 6] = v;
   __syncthreads();
   V r = sh[0];
   for (uint32_t w = 1; w < blockDim.x / 64; ++w) r = sh[w] < r ? sh[w] : r;
@@ -124,8 +186,8 @@ __device__ V block_min(V v, V* sh) {
 }
 
 __device__ uint32_t block_sum(uint32_t v, uint32_t* sh) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  v = team_sum(v, 64u);
+  if ((threadIdx.x & 63) == 63) sh[threadIdx.x >> 6] = v;
   __syncthreads();
   uint32_t r = 0;
   for (uint32_t w = 0; w < blockDim.x / 64; ++w) r += sh[w];
@@ -518,7 +580,7 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
     // inside each cell, and the cell starts locate any run in O(1).  A team
     // of lanes, sized to the mean run length, takes one bucket at a time: each
     // lane walks its share of the run and adds every entry to all rounds (up
-    // to kSubRounds accumulators), and a butterfly of fixed shape closes the
+    // to kSubRounds accumulators), and a fixed sequence of cross-lane adds closes the
     // sums.  The order of every sum depends only on the recovered set, not on
     // how the store was filled.
     if (nrec > 0) {
@@ -610,7 +672,7 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
 #pragma unroll
           for (int jj = 0; jj < kSubRounds; ++jj) acc[jj] = cplx<R>{0, 0};
           cplx<R> yv[kSubRounds];  // this bucket's values, fetched before the sums
-          if (i < B && lane == 0) {
+          if (i < B && lane == S - 1) {
 #pragma unroll
             for (int jj = 0; jj < kSubRounds; ++jj)
               if (uint32_t(jj) < nj) yv[jj] = Y[size_t(j0 + jj) * B + i];
@@ -641,14 +703,12 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
           }
 #pragma unroll
           for (int jj = 0; jj < kSubRounds; ++jj) {
-            if (uint32_t(jj) < nj) {  // nj is uniform
-              for (uint32_t off = S >> 1; off > 0; off >>= 1) {
-                acc[jj].re += __shfl_xor(acc[jj].re, int(off), 64);
-                acc[jj].im += __shfl_xor(acc[jj].im, int(off), 64);
-              }
+            if (uint32_t(jj) < nj) {  // nj is uniform; the sums land in the team's last lane
+              acc[jj].re = team_sum(acc[jj].re, S);
+              acc[jj].im = team_sum(acc[jj].im, S);
             }
           }
-          if (i < B && lane == 0) {
+          if (i < B && lane == S - 1) {
 #pragma unroll
             for (int jj = 0; jj < kSubRounds; ++jj)
               if (uint32_t(jj) < nj) Y[size_t(j0 + jj) * B + i] = csub(yv[jj], acc[jj]);
