@@ -19,7 +19,6 @@ constexpr int kWaves = kRecThreads / 64;
 constexpr int kLdsBytes = 75776;    // one buffer, reused phase by phase; two workgroups still fit a CU
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr int kRegRounds = 16;      // rounds whose estimates are sorted in registers
-constexpr int kSubRounds = 8;       // rounds accumulated together by the subtraction
 constexpr int kVgBatch = 4;         // entries whose loads a thread issues together
 
 struct K128 {
@@ -544,10 +543,16 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
       ++logc;
     }
     const uint32_t nslot = it->reach + 1;  // buckets a coefficient can reach
+    // subtraction scratch: cell ends, sorted keys, values (over the scattered
+    // keys), window weights per (entry, reachable bucket), one round's
+    // value x phase per entry, one round's sums per bucket
+    constexpr uint32_t CB = uint32_t(sizeof(cplx<R>));
     const uint32_t o_sk = (npow * 4u + 15u) & ~15u;
-    const uint32_t o_tmp = (o_sk + nrec * 8u + 15u) & ~15u;
-    const uint32_t vg_bytes = nrec * nslot * uint32_t(sizeof(cplx<R>));
-    const uint32_t sub_need = nrec == 0 ? 0u : o_tmp + (nslot <= 3 && vg_bytes > nrec * 8u ? vg_bytes : nrec * 8u);
+    const uint32_t o_sv = (o_sk + nrec * 8u + 15u) & ~15u;
+    const uint32_t o_gq = (o_sv + nrec * CB + 15u) & ~15u;
+    const uint32_t o_w = (o_gq + nrec * nslot * uint32_t(sizeof(R)) + 15u) & ~15u;
+    const uint32_t o_ys = (o_w + nrec * CB + 15u) & ~15u;
+    const uint32_t sub_need = nrec == 0 ? 0u : o_ys + B * CB;
     const uint32_t det_need = B * uint32_t(sizeof(typename RK::T));
     const uint32_t scr_need = sub_need > det_need ? sub_need : det_need;
     const uint32_t ys_bytes = (R1 * B * uint32_t(sizeof(cplx<R>)) + 15u) & ~15u;
@@ -573,24 +578,27 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
     }
 
     // ---- subtraction of the coefficients recovered so far ----
-    // The store is sorted by its permuted frequency u = sigma f mod N, so the
+    // Sorted by its permuted frequency u = sigma f mod N, the store lists the
     // coefficients that leak into bucket i (circular distance |iL - u| <= D)
-    // form one circular run of the sorted list.  The sort is a counting sort
-    // on the top bits of u (about one entry per cell) followed by exact ranks
-    // inside each cell, and the cell starts locate any run in O(1).  A team
-    // of lanes, sized to the mean run length, takes one bucket at a time: each
-    // lane walks its share of the run and adds every entry to all rounds (up
-    // to kSubRounds accumulators), and a fixed sequence of cross-lane adds closes the
-    // sums.  The order of every sum depends only on the recovered set, not on
-    // how the store was filled.
+    // as one circular run.  The sort is a counting sort on the top bits of u
+    // (about one entry per cell) followed by exact ranks inside each cell;
+    // the cell ends locate any run in O(1).  Then, round by round: every
+    // entry's value times its phase exp(-2 pi i T_j u / N) is formed once,
+    // evenly over the threads; a team of lanes per bucket adds window weight
+    // times that value over the bucket's run, closed by a fixed sequence of
+    // cross-lane adds; and the round's sums are taken off the bucket values
+    // in one pass.  The order of every sum depends only on the recovered set.
     if (nrec > 0) {
       const uint32_t cshift = logN - logc;  // npow <= rec_cap < N
-      // o_tmp is 16-byte aligned: complex128 weights reuse that region
-      const bool in_lds = o_tmp + nrec * 8u <= scr_bytes;
+      const bool in_lds = sub_need <= scr_bytes;
       unsigned char* base = in_lds ? scr : reinterpret_cast<unsigned char*>(gkeys);
       uint32_t* cend = reinterpret_cast<uint32_t*>(base);  // cell counts, then cell ends
       uint64_t* sk = reinterpret_cast<uint64_t*>(base + o_sk);
-      uint64_t* tmp = reinterpret_cast<uint64_t*>(base + o_tmp);
+      uint64_t* tmp = reinterpret_cast<uint64_t*>(base + o_sv);  // scattered keys, then values
+      cplx<R>* sv = reinterpret_cast<cplx<R>*>(base + o_sv);
+      R* gq = reinterpret_cast<R*>(base + o_gq);
+      cplx<R>* w = reinterpret_cast<cplx<R>*>(base + o_w);
+      cplx<R>* ysub = reinterpret_cast<cplx<R>*>(base + o_ys);
       for (uint32_t c = tid; c < npow; c += NT) cend[c] = 0;
       __syncthreads();
       for (uint32_t k = tid; k < nrec; k += NT) atomicAdd(&cend[((sigma * rf[k]) & nmask) >> cshift], 1u);
@@ -619,64 +627,53 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
         while (q < c1 && uint32_t(sk[q] >> 32) < x) ++q;
         return q;
       };
-      // v * Ghat of every entry for each bucket it reaches (slot r: bucket
-      // i0(u) + r, i0 = ceil((u - D) / L)), over the scattered copy, which is
-      // no longer needed.  A thread issues the loads of kVgBatch entries
-      // together, so the team loop below reads LDS only.
-      const bool vg_in_lds = in_lds && nslot <= 3 && o_tmp + vg_bytes <= scr_bytes;
-      cplx<R>* vgs = reinterpret_cast<cplx<R>*>(scr + o_tmp);
-      if (vg_in_lds) {
-        for (uint32_t qb = 0; qb < nrec; qb += kVgBatch * NT) {
-          uint64_t key[kVgBatch];
-          cplx<R> val[kVgBatch];
+      // values in sorted order and the window weight of each bucket an entry
+      // reaches (slot r: bucket i0(u) + r, i0 = ceil((u - D) / L)); a thread
+      // issues the loads of kVgBatch entries together
+      for (uint32_t qb = 0; qb < nrec; qb += kVgBatch * NT) {
+        uint64_t key[kVgBatch];
+        cplx<R> val[kVgBatch];
 #pragma unroll
-          for (int e = 0; e < kVgBatch; ++e) {
-            const uint32_t q = qb + uint32_t(e) * NT + tid;
-            key[e] = q < nrec ? sk[q] : 0;
-          }
+        for (int e = 0; e < kVgBatch; ++e) {
+          const uint32_t q = qb + uint32_t(e) * NT + tid;
+          key[e] = q < nrec ? sk[q] : 0;
+        }
 #pragma unroll
-          for (int e = 0; e < kVgBatch; ++e) {
-            const uint32_t q = qb + uint32_t(e) * NT + tid;
-            val[e] = q < nrec ? rv[uint32_t(key[e])] : cplx<R>{0, 0};
-          }
+        for (int e = 0; e < kVgBatch; ++e) {
+          const uint32_t q = qb + uint32_t(e) * NT + tid;
+          val[e] = q < nrec ? rv[uint32_t(key[e])] : cplx<R>{0, 0};
+        }
 #pragma unroll
-          for (int e = 0; e < kVgBatch; ++e) {
-            const uint32_t q = qb + uint32_t(e) * NT + tid;
-            if (q < nrec) {
-              const int64_t u = int64_t(key[e] >> 32);
-              const int64_t i0 = first_bucket(uint32_t(u), D, it->logL);
-#pragma unroll
-              for (uint32_t r = 0; r < 3; ++r) {
-                if (r < nslot) {
-                  const int64_t dist = (i0 + int64_t(r)) * int64_t(L) - u;
-                  const int64_t ad = dist < 0 ? -dist : dist;
-                  vgs[q * nslot + r] = ad <= int64_t(D) ? cscale(val[e], ghat[ad]) : cplx<R>{0, 0};
-                }
-              }
+        for (int e = 0; e < kVgBatch; ++e) {
+          const uint32_t q = qb + uint32_t(e) * NT + tid;
+          if (q < nrec) {
+            const uint32_t u = uint32_t(key[e] >> 32);
+            const int64_t i0 = first_bucket(u, D, it->logL);
+            sv[q] = val[e];
+            for (uint32_t r = 0; r < nslot; ++r) {
+              const int64_t dist = (i0 + int64_t(r)) * int64_t(L) - int64_t(u);
+              const int64_t ad = dist < 0 ? -dist : dist;
+              gq[q * nslot + r] = ad <= int64_t(D) ? ghat[ad] : R(0);
             }
           }
         }
-        __syncthreads();
       }
-      // team size: smallest power of two >= the mean run length, in [1, 64]
+      __syncthreads();
+      // team size: enough lanes to cover the mean run, as many as let one
+      // pass take all buckets (at least 1, at most 64)
       const double mean_run = double(nrec) * double(2 * D + 1) / double(N);
       uint32_t S = 1;
-      while (S < 64 && double(S) < mean_run) S <<= 1;
+      while (S < 64 && double(S) < mean_run && S * 2u * B <= NT) S <<= 1;
       const uint32_t team = tid / S, lane = tid & (S - 1), nteams = NT / S;
       const uint32_t span = 2 * D + 1;  // < N
-      for (uint32_t j0 = 0; j0 < R1; j0 += kSubRounds) {
-        const uint32_t nj = min(R1 - j0, uint32_t(kSubRounds));
-        for (uint32_t base = 0; base < B; base += nteams) {  // uniform trip count per wave
-          const uint32_t i = base + team;
-          cplx<R> acc[kSubRounds];
-#pragma unroll
-          for (int jj = 0; jj < kSubRounds; ++jj) acc[jj] = cplx<R>{0, 0};
-          cplx<R> yv[kSubRounds];  // this bucket's values, fetched before the sums
-          if (i < B && lane == S - 1) {
-#pragma unroll
-            for (int jj = 0; jj < kSubRounds; ++jj)
-              if (uint32_t(jj) < nj) yv[jj] = Y[size_t(j0 + jj) * B + i];
-          }
+      for (uint32_t j = 0; j < R1; ++j) {
+        const uint32_t Tj = it->T[j];
+        for (uint32_t q = tid; q < nrec; q += NT)
+          w[q] = cmul(sv[q], expi<R>((Tj * uint32_t(sk[q] >> 32)) & nmask, logN, R(-1)));
+        __syncthreads();
+        for (uint32_t base_i = 0; base_i < B; base_i += nteams) {  // uniform trip count per wave
+          const uint32_t i = base_i + team;
+          cplx<R> acc{0, 0};
           if (i < B) {
             const uint32_t a = (i * L - D) & nmask;  // first u of the run
             const uint64_t stop = uint64_t(a) + span;
@@ -685,37 +682,33 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
             for (uint32_t v = lane; v < cnt; v += S) {
               uint32_t q = q0 + v;
               q = q >= nrec ? q - nrec : q;
-              const uint64_t key = sk[q];
-              const uint32_t u = uint32_t(key >> 32);
-              cplx<R> vg;
-              if (vg_in_lds) {
-                const int64_t i0 = first_bucket(u, D, it->logL);
-                vg = vgs[q * nslot + ((i - uint32_t(i0)) & (B - 1))];
-              } else {
-                const uint32_t d1 = (i * L - u) & nmask;
-                vg = cscale(rv[uint32_t(key)], ghat[min(d1, N - d1)]);
-              }
-#pragma unroll
-              for (int jj = 0; jj < kSubRounds; ++jj)
-                if (uint32_t(jj) < nj)
-                  acc[jj] = cadd(acc[jj], cmul(vg, expi<R>((it->T[j0 + jj] * u) & nmask, logN, R(-1))));
+              const uint32_t u = uint32_t(sk[q] >> 32);
+              const uint32_t slot = (i - uint32_t(first_bucket(u, D, it->logL))) & (B - 1);
+              acc = cadd(acc, cscale(w[q], gq[q * nslot + slot]));
             }
           }
+          acc.re = team_sum(acc.re, S);  // the team's sum lands in its last lane
+          acc.im = team_sum(acc.im, S);
+          if (i < B && lane == S - 1) ysub[i] = acc;
+        }
+        __syncthreads();
+        // take the round's sums off the bucket values, loads batched
+        cplx<R>* Yj = Y + size_t(j) * B;
+        for (uint32_t ib = 0; ib < B; ib += kVgBatch * NT) {
+          cplx<R> yv[kVgBatch];
 #pragma unroll
-          for (int jj = 0; jj < kSubRounds; ++jj) {
-            if (uint32_t(jj) < nj) {  // nj is uniform; the sums land in the team's last lane
-              acc[jj].re = team_sum(acc[jj].re, S);
-              acc[jj].im = team_sum(acc[jj].im, S);
-            }
+          for (int e = 0; e < kVgBatch; ++e) {
+            const uint32_t i = ib + uint32_t(e) * NT + tid;
+            if (i < B) yv[e] = Yj[i];
           }
-          if (i < B && lane == S - 1) {
 #pragma unroll
-            for (int jj = 0; jj < kSubRounds; ++jj)
-              if (uint32_t(jj) < nj) Y[size_t(j0 + jj) * B + i] = csub(yv[jj], acc[jj]);
+          for (int e = 0; e < kVgBatch; ++e) {
+            const uint32_t i = ib + uint32_t(e) * NT + tid;
+            if (i < B) Yj[i] = csub(yv[e], ysub[i]);
           }
         }
+        __syncthreads();
       }
-      __syncthreads();
     }
 
     // ---- singleton detection ----
