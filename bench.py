@@ -124,6 +124,7 @@ def main():
     ap.add_argument("--layout", default="position-major", choices=["position-major", "per-signal"],
                     help="batch storage: sample c of signal s at X[c, s] (one plan), or one buffer per signal")
     ap.add_argument("--no-context", action="store_true", help="skip timing the other layout")
+    ap.add_argument("--no-forms", action="store_true", help="skip the FP16 and uneven-batch context lines")
     ap.add_argument("--fold-config", default=None, metavar="U,CAP",
                     help="fold launch shape (taps per thread, workgroups per CU cap) instead of tuning")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -175,29 +176,20 @@ def main():
         XT = X.transpose(0, 1).contiguous()
         torch.cuda.synchronize()
 
-    def run_layout(layout, steps):
-        """Bind, tune, warm up and time `steps` passes of the batch in one layout."""
-        if layout == "position-major":
-            batch = sfft.InterleavedBatch(plan, n)
-            outs = batch.outputs(dev)
-            run = lambda: batch.execute(XT, scales=scales, outs=outs)  # noqa: E731
-        else:
-            batch = sfft.Batch([plan] * n)
-            outs = batch.outputs(dev)
-            xs = [X[i] for i in range(n)]
-            run = lambda: batch.execute(xs, scales=scales, outs=outs)  # noqa: E731
+    def time_batch(batch, run, steps, tag, position_major):
+        """Bind, tune, warm up and time `steps` passes of a bound batch."""
         run()  # binds buffers, builds the graph
         torch.cuda.synchronize()
         fold_cfg = None
         if args.fold_config:
             u, cap = (int(v) for v in args.fold_config.split(","))
-            cap = 0 if layout == "position-major" else cap
+            cap = 0 if position_major else cap
             batch.set_fold_config(u, cap)
             fold_cfg = {"unroll": u, "wg_per_cu": cap, "fold_ms": None}
         elif not args.no_autotune:
             t1 = time.perf_counter()
             fold_cfg = batch.autotune()
-            log(f"[{layout}] fold autotune: {fold_cfg} in {time.perf_counter() - t1:.1f}s")
+            log(f"[{tag}] fold autotune: {fold_cfg} in {time.perf_counter() - t1:.1f}s")
         run()  # captures with the chosen launch shape
         torch.cuda.synchronize()
         for _ in range(args.warmup):
@@ -225,12 +217,110 @@ def main():
             run()
         torch.cuda.synchronize()
         graph_ms = (time.perf_counter() - tg) * 1e3 / steps
-        res = {"layout": layout, "value": n * steps / elapsed, "ms_per_step": elapsed * 1e3 / steps,
-               "stage_ms": stage_ms, "graph_ms_per_step": graph_ms, "fold_cfg": fold_cfg, "outs": outs}
-        log(f"[{layout}] timed {steps} steps: {res['ms_per_step']:.3f} ms/step, {res['value']:.1f} signals/s; "
+        nsig = len(batch.plans)
+        res = {"value": nsig * steps / elapsed, "ms_per_step": elapsed * 1e3 / steps,
+               "stage_ms": stage_ms, "graph_ms_per_step": graph_ms, "fold_cfg": fold_cfg}
+        log(f"[{tag}] timed {steps} steps: {res['ms_per_step']:.3f} ms/step, {res['value']:.1f} signals/s; "
             f"stages ms {[round(v, 4) for v in stage_ms]}; graph {graph_ms:.3f} ms/step")
+        return res
+
+    def run_layout(layout, steps):
+        """The metric batch in one layout: bind, tune, warm up, time."""
+        if layout == "position-major":
+            batch = sfft.InterleavedBatch(plan, n)
+            outs = batch.outputs(dev)
+            run = lambda: batch.execute(XT, scales=scales, outs=outs)  # noqa: E731
+        else:
+            batch = sfft.Batch([plan] * n)
+            outs = batch.outputs(dev)
+            xs = [X[i] for i in range(n)]
+            run = lambda: batch.execute(xs, scales=scales, outs=outs)  # noqa: E731
+        res = time_batch(batch, run, steps, layout, layout == "position-major")
+        res["layout"] = layout
+        res["outs"] = outs
         batch.close()
         return res
+
+    def precision_form(steps):
+        """The same signals stored as FP16 (re, im) pairs with a per-signal FP32
+        scale (max |re|, |im|), position-major; window and sums in FP32."""
+        X16 = torch.empty((N, n, 2), dtype=torch.float16, device=dev)
+        sc16 = []
+        for c0 in range(0, n, 64):
+            xc = X[c0:c0 + 64]
+            sc = torch.maximum(xc.real.abs().amax(1), xc.imag.abs().amax(1))
+            h = torch.stack([xc.real / sc[:, None], xc.imag / sc[:, None]], -1).to(torch.float16)
+            X16[:, c0:c0 + 64] = h.transpose(0, 1)
+            sc16 += [float(v) for v in sc.cpu()]
+            del xc, h
+        torch.cuda.synchronize()
+        plan16 = sfft.Plan(N, K, B, w, M, l, q, delta=delta, seed=plan_seed, dtype="f16x2")
+        b16 = sfft.InterleavedBatch(plan16, n)
+        outs16 = b16.outputs(dev)
+        r = time_batch(b16, lambda: b16.execute(X16, scales=sc16, outs=outs16), steps, "precision f16x2", True)
+        b16.close()
+        alg = n * (plan16.samples * 4 + plan16.yhat_elems * 8)
+        line = {"storage": "f16 pairs + per-signal f32 scale", "layout": "position-major",
+                "signals_per_s": round(r["value"], 1), "ms_per_step": round(r["ms_per_step"], 4),
+                "stage_ms": {"fold": round(r["stage_ms"][0], 4), "bucket_fft": round(r["stage_ms"][1], 4),
+                             "recover": round(r["stage_ms"][2], 4)},
+                "fold_alg_gbs": round(alg / (r["stage_ms"][0] * 1e-3) / 1e9, 1),
+                "fold_alg_frac": round(alg / (r["stage_ms"][0] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "fold_launch": r["fold_cfg"]}
+        return line, (X16, sc16, outs16)
+
+    def batching_form(steps):
+        """512 signals of uneven N, K and SNR, one plan each, one buffer each:
+        N = 2^U{16..22}, K log-uniform on [10, 2000], SNR uniform on [10, 40] dB;
+        B = 2^ceil(log2 2K) capped at N/32 (so that w = B log2 N | 1 < N),
+        K capped at B/2, loops = ceil(log2 K) + 2, (l, q) = (16, 1);
+        seeds 401 + i (signal draws) and 402 + i (plan)."""
+        from paper_2011_05698_amd.signals import planted_spectrum
+
+        from concurrent.futures import ThreadPoolExecutor
+
+        nb = n
+        xs_b, spec = [], []
+        for i in range(nb):
+            g = np.random.default_rng(401 + i)
+            ln = int(g.integers(16, 23))
+            Ni = 1 << ln
+            Ki = int(round(math.exp(g.uniform(math.log(10), math.log(2000)))))
+            snr = float(g.uniform(10, 40))
+            Bi = min(1 << math.ceil(math.log2(2 * Ki)), Ni // 32)
+            Ki = min(Ki, Bi // 2)
+            Mi = math.ceil(math.log2(Ki)) + 2
+            spec.append((Ni, Ki, Bi, (Bi * ln) | 1, Mi, snr))
+        t1 = time.perf_counter()
+        with ThreadPoolExecutor(max_workers=16) as ex:  # plan synthesis is host work; the C calls drop the GIL
+            plans_b = list(ex.map(lambda i: sfft.Plan(*spec[i][:5], l, q, delta=delta, seed=402 + i), range(nb)))
+        log(f"[batching uneven] {nb} plans built in {time.perf_counter() - t1:.1f}s")
+        gen = torch.Generator(device=dev)
+        for i in range(nb):
+            Ni, Ki, Bi, wi, Mi, snr = spec[i]
+            sup, vals = planted_spectrum(Ni, Ki, 401 + i)
+            xh = torch.zeros(Ni, dtype=torch.complex128, device=dev)
+            xh[torch.from_numpy(sup).to(dev)] = torch.from_numpy(vals).to(dev)
+            x = torch.fft.ifft(xh) * Ni
+            gen.manual_seed(401 + i + 0x5EED)
+            s2 = float((x.abs() ** 2).sum()) / Ni * 10.0 ** (-snr / 10.0)
+            x = x + torch.randn(Ni, dtype=torch.complex128, device=dev, generator=gen) * math.sqrt(s2)
+            xs_b.append(x.to(torch.complex64))
+        torch.cuda.synchronize()
+        bb = sfft.Batch(plans_b)
+        outs_b = bb.outputs(dev)
+        r = time_batch(bb, lambda: bb.execute(xs_b, outs=outs_b), steps, "batching uneven", False)
+        bb.close()
+        samples = sum(p.samples for p in plans_b)
+        alg = samples * 8 + sum(p.yhat_elems for p in plans_b) * 8
+        line = {"signals": nb, "N": "2^16..2^22", "K": "10..2000", "snr_db": "10..40", "layout": "per-signal",
+                "signals_per_s": round(r["value"], 1), "ms_per_step": round(r["ms_per_step"], 4),
+                "stage_ms": {"fold": round(r["stage_ms"][0], 4), "bucket_fft": round(r["stage_ms"][1], 4),
+                             "recover": round(r["stage_ms"][2], 4)},
+                "graph_ms_per_step": round(r["graph_ms_per_step"], 4),
+                "fold_alg_gbs": round(alg / (r["stage_ms"][0] * 1e-3) / 1e9, 1),
+                "fold_launch": r["fold_cfg"]}
+        return line, (xs_b, spec, outs_b)
 
     main_res = run_layout(args.layout, args.steps)
     context = None
@@ -241,6 +331,12 @@ def main():
                    "stage_ms": {"fold": round(r["stage_ms"][0], 4), "bucket_fft": round(r["stage_ms"][1], 4),
                                 "recover": round(r["stage_ms"][2], 4)},
                    "fold_launch": r["fold_cfg"]}
+    # ---- the two other forms of the method (context lines) ----
+    forms, form_outs = {}, {}
+    if not args.no_forms and dt == "c64":
+        forms["precision"], form_outs["precision"] = precision_form(max(2, args.steps // 2))
+        forms["batching"], form_outs["batching"] = batching_form(max(2, args.steps // 2))
+
     K_steps = args.steps
     stage_ms, ms_per_step, value = main_res["stage_ms"], main_res["ms_per_step"], main_res["value"]
     graph_ms, fold_cfg, outs = main_res["graph_ms_per_step"], main_res["fold_cfg"], main_res["outs"]
@@ -314,6 +410,39 @@ def main():
                "sample": f"first {done} signals of the batch (same inputs), FP64 NumPy oracle, plan untimed"}
         parity = {"signals_checked": done, "support_identical": same, "max_rel_l2_identical": worst}
         log(f"oracle: {done} signals in {spent:.1f}s; parity {same}/{done}, max rel-L2 {worst:.2e}")
+        # the other forms, a few signals each (not timed)
+        if "precision" in form_outs:
+            X16, sc16, (i16, v16, c16) = form_outs["precision"]
+            P16 = O.make_plan(N, K, B, w, M, l, Fraction(q), delta, seed=plan_seed)
+            chk, same16, worst16 = 0, 0, 0.0
+            for s_ in range(2):
+                h = X16[:, s_].float().cpu().numpy().astype(np.float64)
+                oi, ov, _ = O.sfft((h[:, 0] + 1j * h[:, 1]) * sc16[s_], P16)
+                c = int(c16[s_].item())
+                gi, gv = i16[s_, :c].cpu().numpy(), v16[s_, :c].cpu().numpy().astype(np.complex128)
+                chk += 1
+                if np.array_equal(gi, oi):
+                    same16 += 1
+                    worst16 = max(worst16, float(np.linalg.norm(gv - ov) / max(np.linalg.norm(ov), 1e-300)))
+            forms["precision"]["parity"] = {"signals_checked": chk, "support_identical": same16,
+                                            "max_rel_l2_identical": worst16,
+                                            "oracle_input": "the dequantized FP16 samples"}
+        if "batching" in form_outs:
+            xs_b, spec, (ib, vb, cb) = form_outs["batching"]
+            agree, worst_b = [], 0.0
+            for s_ in range(4):
+                Ni, Ki, Bi, wi, Mi, snr = spec[s_]
+                Pb = O.make_plan(Ni, Ki, Bi, wi, Mi, l, Fraction(q), delta, seed=402 + s_)
+                oi, ov, _ = O.sfft(xs_b[s_].cpu().numpy().astype(np.complex128), Pb)
+                c = int(cb[s_].item())
+                gi, gv = ib[s_][:c].cpu().numpy(), vb[s_][:c].cpu().numpy().astype(np.complex128)
+                common, ga, oa = np.intersect1d(gi, oi, return_indices=True)
+                agree.append(len(common) / max(len(oi), len(gi), 1))
+                if len(common):
+                    worst_b = max(worst_b, float(np.linalg.norm(gv[ga] - ov[oa]) / max(np.linalg.norm(ov[oa]), 1e-300)))
+            forms["batching"]["parity"] = {"signals_checked": len(agree), "min_support_agreement": round(min(agree), 4),
+                                           "max_rel_l2_common": worst_b,
+                                           "note": "noisy inputs: decisions near the threshold may flip"}
 
     line = {
         "metric": METRIC, "value": round(value, 2), "unit": "signals/s", "n_gpus": 1, "steps": K_steps,
@@ -332,6 +461,7 @@ def main():
         "graph_ms_per_step": round(graph_ms, 4),
         "fold_launch": fold_cfg,
         "other_layout": context,
+        "forms": forms or None,
     }
     print(json.dumps(line), flush=True)
 

@@ -181,6 +181,32 @@ def test_noisy_support_agreement(sf):
     assert rel_l2(a, b) <= 1e-3
 
 
+@pytest.mark.parametrize("snr", [None, 30], ids=["noiseless", "snr30"])
+def test_precision_form_shape(sf, snr):
+    """The precision form's workload shape: N = 2^24, K = 4000, B = 8192,
+    w = 196609, 14 iterations, complex64 storage, Kahan-compensated fold,
+    location phases in FP64 (N >= 2^24).  Noiseless: the oracle's support
+    bit for bit and values within 1e-4; 30 dB: supports agree almost
+    everywhere, common values within FP32 noise."""
+    N, K, B, w, M, l, q, delta = 2 ** 24, 4000, 8192, 196609, 14, 16, Fraction(1), 1e-6
+    x, sup, _ = make_signal(SignalSpec(N, K, 301, snr))
+    xd, scale, xq = to_dev(x, "c64")
+    P = O.make_plan(N, K, B, w, M, l, q, delta, seed=302)
+    oidx, oval, _ = O.sfft(xq, P)
+    plan = sf.Plan(N, K, B, w, M, l, q, delta=delta, seed=302, kahan=True)
+    gidx, gval, c = run_gpu(sf, plan, xd, scale)
+    if snr is None:
+        assert np.array_equal(oidx, np.sort(sup))
+        assert np.array_equal(gidx, oidx)
+        assert rel_l2(gval, oval) <= 1e-4
+    else:
+        common = np.intersect1d(gidx, oidx)
+        assert len(common) >= 0.99 * len(oidx), (len(common), len(oidx))
+        gi = {f: v for f, v in zip(gidx, gval)}
+        oi = {f: v for f, v in zip(oidx, oval)}
+        assert rel_l2(np.array([gi[f] for f in common]), np.array([oi[f] for f in common])) <= 1e-3
+
+
 def test_batch_uneven_matches_single(sf):
     """Signals of different N and K in one batch give exactly what single
     executes give, and match the oracle."""
