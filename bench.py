@@ -125,6 +125,8 @@ def main():
                     help="batch storage: sample c of signal s at X[c, s] (one plan), or one buffer per signal")
     ap.add_argument("--no-context", action="store_true", help="skip timing the other layout")
     ap.add_argument("--no-forms", action="store_true", help="skip the FP16 and uneven-batch context lines")
+    ap.add_argument("--large-form", type=int, default=0, metavar="SIGNALS",
+                    help="also time the N=2^27, K=8192, B=16384 FP16 workload on this many signals")
     ap.add_argument("--fold-config", default=None, metavar="U,CAP",
                     help="fold launch shape (taps per thread, workgroups per CU cap) instead of tuning")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -322,6 +324,71 @@ def main():
                 "fold_launch": r["fold_cfg"]}
         return line, (xs_b, spec, outs_b)
 
+    def large_form(nl, steps):
+        """The large reduced-precision workload: N = 2^27, K = 8192, magnitudes
+        log-uniform on [1e-2, 1], 40 dB, B = 16384, w = 16384 * 27 + 1, 15
+        iterations, FP16 pairs with a per-signal scale (position-major, one
+        plan); compared with the planted support and with the FP32 path on the
+        same signals (seeds 501 + i / plan 502)."""
+        from paper_2011_05698_amd.signals import planted_spectrum
+
+        NL, KL, BL, ML = 2 ** 27, 8192, 16384, 15
+        wl = (BL * 27) | 1
+        X32 = torch.empty((NL, nl), dtype=torch.complex64, device=dev)
+        X16 = torch.empty((NL, nl, 2), dtype=torch.float16, device=dev)
+        sc, sups = [], []
+        gen = torch.Generator(device=dev)
+        for i in range(nl):
+            sup, vals = planted_spectrum(NL, KL, 501 + i, mags="loguniform")
+            xh = torch.zeros(NL, dtype=torch.complex128, device=dev)
+            xh[torch.from_numpy(sup).to(dev)] = torch.from_numpy(vals).to(dev)
+            x = torch.fft.ifft(xh) * NL
+            del xh
+            gen.manual_seed(501 + i + 0x5EED)
+            s2 = float((x.abs() ** 2).sum()) / NL * 10.0 ** (-40 / 10.0)
+            x = x + torch.randn(NL, dtype=torch.complex128, device=dev, generator=gen) * math.sqrt(s2)
+            X32[:, i] = x.to(torch.complex64)
+            m = float(torch.maximum(x.real.abs().max(), x.imag.abs().max()))
+            X16[:, i, 0] = (x.real / m).to(torch.float16)
+            X16[:, i, 1] = (x.imag / m).to(torch.float16)
+            sc.append(m)
+            sups.append(sup)
+            del x
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        p16 = sfft.Plan(NL, KL, BL, wl, ML, l, q, delta=delta, seed=502, dtype="f16x2")
+        p32 = sfft.Plan(NL, KL, BL, wl, ML, l, q, delta=delta, seed=502)
+        log(f"[large f16x2] plans built in {time.perf_counter() - t1:.1f}s")
+        b16 = sfft.InterleavedBatch(p16, nl)
+        o16 = b16.outputs(dev)
+        r = time_batch(b16, lambda: b16.execute(X16, scales=sc, outs=o16), steps, "large f16x2", True)
+        b16.close()
+        b32 = sfft.InterleavedBatch(p32, nl)
+        o32 = b32.execute(X32)
+        torch.cuda.synchronize()
+        b32.close()
+        recall16, recall32, agree, worst = [], [], [], 0.0
+        for i in range(nl):
+            c16, c32 = int(o16[2][i].item()), int(o32[2][i].item())
+            g16, g32 = o16[0][i, :c16].cpu().numpy(), o32[0][i, :c32].cpu().numpy()
+            v16 = o16[1][i, :c16].cpu().numpy().astype(np.complex128)
+            v32 = o32[1][i, :c32].cpu().numpy().astype(np.complex128)
+            recall16.append(len(np.intersect1d(g16, sups[i])) / KL)
+            recall32.append(len(np.intersect1d(g32, sups[i])) / KL)
+            common, a16, a32 = np.intersect1d(g16, g32, return_indices=True)
+            agree.append(len(common) / max(len(g32), 1))
+            worst = max(worst, float(np.linalg.norm(v16[a16] - v32[a32]) / max(np.linalg.norm(v32[a32]), 1e-300)))
+        alg = nl * (p16.samples * 4 + p16.yhat_elems * 8)
+        return {"N": NL, "K": KL, "B": BL, "w": wl, "loops": ML, "signals": nl, "snr_db": 40,
+                "mags": "log-uniform [1e-2, 1]", "storage": "f16 pairs + per-signal f32 scale",
+                "signals_per_s": round(r["value"], 2), "ms_per_step": round(r["ms_per_step"], 3),
+                "stage_ms": {"fold": round(r["stage_ms"][0], 4), "bucket_fft": round(r["stage_ms"][1], 4),
+                             "recover": round(r["stage_ms"][2], 4)},
+                "fold_alg_gbs": round(alg / (r["stage_ms"][0] * 1e-3) / 1e9, 1),
+                "recall_f16": round(float(np.mean(recall16)), 4), "recall_f32": round(float(np.mean(recall32)), 4),
+                "support_agreement_f16_vs_f32": round(float(np.min(agree)), 4),
+                "max_rel_l2_f16_vs_f32_common": worst}
+
     main_res = run_layout(args.layout, args.steps)
     context = None
     if not args.no_context:
@@ -336,6 +403,8 @@ def main():
     if not args.no_forms and dt == "c64":
         forms["precision"], form_outs["precision"] = precision_form(max(2, args.steps // 2))
         forms["batching"], form_outs["batching"] = batching_form(max(2, args.steps // 2))
+    if args.large_form:
+        forms["large_precision"] = large_form(args.large_form, max(2, args.steps // 2))
 
     K_steps = args.steps
     stage_ms, ms_per_step, value = main_res["stage_ms"], main_res["ms_per_step"], main_res["value"]

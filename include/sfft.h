@@ -96,8 +96,9 @@ void sfft_default_options(sfft_options* opt);
  * tabulated exactly (FP64) out to L/2 + e, e = ceil of the transition
  * half-width.  The location schedule (Sec. 3.2) and the per-iteration
  * sigma_m (odd) and tau0_m come from SplitMix64(seed).
- * Limits (SFFT_ERR_UNSUPPORTED): B <= 8192 for SFFT_C64/SFFT_F16X2_SCALED,
- * B <= 4096 for SFFT_C128; at most 47 location steps per iteration.
+ * Limits (SFFT_ERR_UNSUPPORTED): B <= 16384 for SFFT_C64/SFFT_F16X2_SCALED,
+ * B <= 8192 for SFFT_C128 (the bucket DFT keeps B values in 128 KiB of LDS);
+ * at most 47 location steps per iteration.
  * On success *out holds a plan owning its tables and workspace.
  */
 sfft_status sfft_plan(sfft_plan_t* out, int64_t N, int64_t K, int64_t B, int64_t w, int32_t loops,

@@ -40,10 +40,23 @@ int launch_bucket_fft(int dtype, const SigArg& sig, const RoundItem* d_items, ui
   if (nitems == 0) return hipSuccess;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   dim3 grid(nitems), block(256);
+  // up to 128 KiB of dynamic LDS (gfx950 gives a workgroup 160 KiB)
   if (dtype == SFFT_C128) {
-    hipLaunchKernelGGL(bucket_fft_kernel<double>, grid, block, size_t(max_B) * 16, s, sig, d_items);
+    const size_t lds = size_t(max_B) * 16;
+    if (lds > 65536) {
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&bucket_fft_kernel<double>),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(bucket_fft_kernel<double>, grid, block, lds, s, sig, d_items);
   } else {
-    hipLaunchKernelGGL(bucket_fft_kernel<float>, grid, block, size_t(max_B) * 8, s, sig, d_items);
+    const size_t lds = size_t(max_B) * 8;
+    if (lds > 65536) {
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&bucket_fft_kernel<float>),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(bucket_fft_kernel<float>, grid, block, lds, s, sig, d_items);
   }
   return hipGetLastError();
 }

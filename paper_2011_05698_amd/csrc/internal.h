@@ -12,8 +12,8 @@ namespace sfft {
 
 constexpr int kMaxRounds = 48;      // R + 1 <= kMaxRounds (reference round + location steps)
 constexpr int kMaxLoops = 64;
-constexpr int kMaxBucketsF32 = 8192;
-constexpr int kMaxBucketsF64 = 4096;
+constexpr int kMaxBucketsF32 = 16384;  // the bucket DFT holds B values in LDS: 128 KiB
+constexpr int kMaxBucketsF64 = 8192;   // 128 KiB of complex128
 
 // One iteration of the method, as the kernels read it (plain data, device copy).
 struct IterDesc {

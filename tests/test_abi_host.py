@@ -90,8 +90,15 @@ def test_paper_literal_parameter_pairs_are_rejected():
 
 
 def test_unsupported_bucket_count():
+    """The bucket DFT holds B values in 128 KiB of LDS: B <= 16384 for the
+    FP32 and FP16 forms, B <= 8192 for complex128."""
+    sfft.Plan(2 ** 20, 100, 16384, 16384 * 20 + 1, 2, 16, 1.0, host_only=True)
+    sfft.Plan(2 ** 20, 100, 8192, 8192 * 20 + 1, 2, 16, 1.0, dtype="c128", host_only=True)
     with pytest.raises(sfft.SfftError) as ei:
-        sfft.Plan(2 ** 20, 100, 16384, 16384 * 20 + 1, 2, 16, 1.0, host_only=True)
+        sfft.Plan(2 ** 22, 100, 32768, 32768 * 22 + 1, 2, 16, 1.0, host_only=True)
+    assert ei.value.status == 2
+    with pytest.raises(sfft.SfftError) as ei:
+        sfft.Plan(2 ** 20, 100, 16384, 16384 * 20 + 1, 2, 16, 1.0, dtype="c128", host_only=True)
     assert ei.value.status == 2
 
 
