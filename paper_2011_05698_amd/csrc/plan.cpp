@@ -272,11 +272,11 @@ void layout_workspace(HostPlan& hp) {
   pd.off_candu = take(uint64_t(pd.Bmax) * 4);
   pd.off_candd = take(uint64_t(pd.Bmax) * 4);
   pd.off_candv = take(uint64_t(pd.Bmax) * 2 * rs);
-  // subtraction scratch when it does not fit in LDS (cell ends, keys, values, up to three
-  // weights per entry, one round's values and bucket sums), or top-K keys
+  // subtraction scratch when it does not fit in LDS (cell ends, keys, values, window
+  // weights per reachable bucket, one round's values, run bounds and bucket sums), or top-K keys
   uint64_t max_slots = 1;
   for (auto& it : hp.iters) max_slots = std::max<uint64_t>(max_slots, uint64_t(it.d.reach) + 1);
-  pd.off_keys = take(uint64_t(pd.sort_cap) * (4 + 8 + 16 + 8 * max_slots + 16) + uint64_t(pd.Bmax) * 16 + 256);
+  pd.off_keys = take(uint64_t(pd.sort_cap) * (4 + 8 + 16 + 8 * max_slots + 16) + uint64_t(pd.Bmax) * 24 + 512);
   pd.off_p0 = take(uint64_t(pd.Bmax) * rs);
   pd.ws_bytes = off;
 }

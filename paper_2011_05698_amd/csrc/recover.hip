@@ -225,6 +225,11 @@ __device__ K block_select(const K* keys, uint32_t n, uint32_t k, uint32_t* hist,
   return prefix;
 }
 
+// The run of sorted store entries that reach one bucket.
+struct RunBounds {
+  uint32_t first, count;
+};
+
 // Block-wide copy of a descriptor (a multiple of 4 bytes) into LDS.
 __device__ __forceinline__ void copy_words(void* dst, const void* src, size_t bytes) {
   for (uint32_t w = threadIdx.x; w < bytes / 4; w += blockDim.x)
@@ -551,14 +556,17 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
     const uint32_t o_sv = (o_sk + nrec * 8u + 15u) & ~15u;
     const uint32_t o_gq = (o_sv + nrec * CB + 15u) & ~15u;
     const uint32_t o_w = (o_gq + nrec * nslot * uint32_t(sizeof(R)) + 15u) & ~15u;
-    const uint32_t o_ys = (o_w + nrec * CB + 15u) & ~15u;
-    const uint32_t sub_need = nrec == 0 ? 0u : o_ys + B * CB;
+    const uint32_t o_run = (o_w + nrec * CB + 15u) & ~15u;  // per bucket: first entry and length of its run
+    const uint32_t o_ys = o_run + B * 8u;                   // one round's sums (bucket values in the workspace)
+    const uint32_t sub_lds_y = nrec == 0 ? 0u : o_ys;       // with the bucket block staged in LDS
+    const uint32_t sub_ws_y = nrec == 0 ? 0u : o_ys + B * CB;
     const uint32_t det_need = B * uint32_t(sizeof(typename RK::T));
-    const uint32_t scr_need = sub_need > det_need ? sub_need : det_need;
     const uint32_t ys_bytes = (R1 * B * uint32_t(sizeof(cplx<R>)) + 15u) & ~15u;
     const uint32_t pb_bytes = ((B * uint32_t(sizeof(R)) + 15u) & ~15u) + 2u * ((B * 4u + 15u) & ~15u) +
                               B * uint32_t(sizeof(cplx<R>));
-    const bool y_lds = ys_bytes + scr_need <= uint32_t(kLdsBytes);
+    const bool y_lds = ys_bytes + (sub_lds_y > det_need ? sub_lds_y : det_need) <= uint32_t(kLdsBytes);
+    const uint32_t sub_need = y_lds ? sub_lds_y : sub_ws_y;
+    const uint32_t scr_need = sub_need > det_need ? sub_need : det_need;
     const uint32_t pb_at = y_lds ? ys_bytes : 0u;
     const bool pb_lds = pb_at + pb_bytes + scr_need <= uint32_t(kLdsBytes);
     const uint32_t scr_at = (pb_at + (pb_lds ? pb_bytes : 0u) + 15u) & ~15u;
@@ -598,6 +606,7 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
       cplx<R>* sv = reinterpret_cast<cplx<R>*>(base + o_sv);
       R* gq = reinterpret_cast<R*>(base + o_gq);
       cplx<R>* w = reinterpret_cast<cplx<R>*>(base + o_w);
+      RunBounds* run = reinterpret_cast<RunBounds*>(base + o_run);
       cplx<R>* ysub = reinterpret_cast<cplx<R>*>(base + o_ys);
       for (uint32_t c = tid; c < npow; c += NT) cend[c] = 0;
       __syncthreads();
@@ -659,13 +668,22 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
         }
       }
       __syncthreads();
+      // every bucket's run: its first entry and its length (the same in every round)
+      const uint32_t span = 2 * D + 1;  // < N
+      for (uint32_t i = tid; i < B; i += NT) {
+        const uint32_t a = (i * L - D) & nmask;  // first u of the run
+        const uint64_t stop = uint64_t(a) + span;
+        const uint32_t q0 = lower(a);
+        const uint32_t cnt = stop <= N ? lower(uint32_t(stop)) - q0 : nrec - q0 + lower(uint32_t(stop - N));
+        run[i] = RunBounds{q0, cnt};
+      }
+      __syncthreads();
       // team size: enough lanes to cover the mean run, as many as let one
       // pass take all buckets (at least 1, at most 64)
       const double mean_run = double(nrec) * double(2 * D + 1) / double(N);
       uint32_t S = 1;
       while (S < 64 && double(S) < mean_run && S * 2u * B <= NT) S <<= 1;
       const uint32_t team = tid / S, lane = tid & (S - 1), nteams = NT / S;
-      const uint32_t span = 2 * D + 1;  // < N
       for (uint32_t j = 0; j < R1; ++j) {
         const uint32_t Tj = it->T[j];
         for (uint32_t q = tid; q < nrec; q += NT)
@@ -675,10 +693,8 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
           const uint32_t i = base_i + team;
           cplx<R> acc{0, 0};
           if (i < B) {
-            const uint32_t a = (i * L - D) & nmask;  // first u of the run
-            const uint64_t stop = uint64_t(a) + span;
-            const uint32_t q0 = lower(a);
-            const uint32_t cnt = stop <= N ? lower(uint32_t(stop)) - q0 : nrec - q0 + lower(uint32_t(stop - N));
+            const RunBounds rb = run[i];
+            const uint32_t q0 = rb.first, cnt = rb.count;
             for (uint32_t v = lane; v < cnt; v += S) {
               uint32_t q = q0 + v;
               q = q >= nrec ? q - nrec : q;
@@ -689,10 +705,14 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
           }
           acc.re = team_sum(acc.re, S);  // the team's sum lands in its last lane
           acc.im = team_sum(acc.im, S);
-          if (i < B && lane == S - 1) ysub[i] = acc;
+          if (i < B && lane == S - 1) {
+            if (y_lds) Y[size_t(j) * B + i] = csub(Y[size_t(j) * B + i], acc);  // staged block: in place
+            else ysub[i] = acc;
+          }
         }
         __syncthreads();
-        // take the round's sums off the bucket values, loads batched
+        if (y_lds) continue;
+        // bucket values in the workspace: take the round's sums off, loads batched
         cplx<R>* Yj = Y + size_t(j) * B;
         for (uint32_t ib = 0; ib < B; ib += kVgBatch * NT) {
           cplx<R> yv[kVgBatch];
