@@ -372,15 +372,15 @@ __device__ __forceinline__ void cswap(R& a, R& b) {
   b = hi;
 }
 
-// Bitonic network on a register array of kRegRounds values (compile-time indices).
-template <typename R>
-__device__ __forceinline__ void sort_regs(R (&v)[kRegRounds]) {
+// Bitonic network on a register array of NR values (compile-time indices).
+template <int NR, typename R>
+__device__ __forceinline__ void sort_regs(R (&v)[NR]) {
 #pragma unroll
-  for (int k = 2; k <= kRegRounds; k <<= 1)
+  for (int k = 2; k <= NR; k <<= 1)
 #pragma unroll
     for (int j = k >> 1; j > 0; j >>= 1)
 #pragma unroll
-      for (int i = 0; i < kRegRounds; ++i) {
+      for (int i = 0; i < NR; ++i) {
         const int ixj = i ^ j;
         if (ixj > i) {
           if ((i & k) == 0) cswap(v[i], v[ixj]);
@@ -389,12 +389,12 @@ __device__ __forceinline__ void sort_regs(R (&v)[kRegRounds]) {
       }
 }
 
-template <typename R>
-__device__ __forceinline__ R pick_median(const R (&v)[kRegRounds], uint32_t n) {
+template <int NR, typename R>
+__device__ __forceinline__ R pick_median(const R (&v)[NR], uint32_t n) {
   const uint32_t lo = (n - 1) / 2, hi = n / 2;
   R a = 0, b = 0;
 #pragma unroll
-  for (int q = 0; q < kRegRounds; ++q) {
+  for (int q = 0; q < NR; ++q) {
     if (uint32_t(q) == lo) a = v[q];
     if (uint32_t(q) == hi) b = v[q];
   }
@@ -403,27 +403,35 @@ __device__ __forceinline__ R pick_median(const R (&v)[kRegRounds], uint32_t n) {
 
 // Median over the R+1 rounds, real and imaginary parts separately; the mean
 // of the two middle values for an even count.
+// The R+1 round estimates sorted in registers (a network of NR >= R+1).
+template <int NR, typename R>
+__device__ __forceinline__ cplx<R> median_in_regs(const cplx<R>* Y, const IterDesc* it, uint32_t i, uint32_t u,
+                                                  uint32_t nmask, uint32_t logN, R g, uint32_t n) {
+  R vr[NR], vi[NR];
+#pragma unroll
+  for (int j = 0; j < NR; ++j) {
+    if (uint32_t(j) < n) {
+      const cplx<R> e = round_estimate(Y, it->B, i, uint32_t(j), it->T[j], u, nmask, logN, g);
+      vr[j] = e.re;
+      vi[j] = e.im;
+    } else {
+      vr[j] = R(INFINITY);
+      vi[j] = R(INFINITY);
+    }
+  }
+  sort_regs<NR>(vr);
+  sort_regs<NR>(vi);
+  return {pick_median<NR>(vr, n), pick_median<NR>(vi, n)};
+}
+
+// Median over the R+1 rounds, real and imaginary parts separately; the mean
+// of the two middle values for an even count.
 template <typename R>
 __device__ cplx<R> median_estimate(const cplx<R>* Y, const IterDesc* it, uint32_t i, uint32_t u, uint32_t nmask,
                                    uint32_t logN, R g) {
   const uint32_t B = it->B, n = it->R + 1;
-  if (n <= uint32_t(kRegRounds)) {
-    R vr[kRegRounds], vi[kRegRounds];
-#pragma unroll
-    for (int j = 0; j < kRegRounds; ++j) {
-      if (uint32_t(j) < n) {
-        const cplx<R> e = round_estimate(Y, B, i, uint32_t(j), it->T[j], u, nmask, logN, g);
-        vr[j] = e.re;
-        vi[j] = e.im;
-      } else {
-        vr[j] = R(INFINITY);
-        vi[j] = R(INFINITY);
-      }
-    }
-    sort_regs(vr);
-    sort_regs(vi);
-    return {pick_median(vr, n), pick_median(vi, n)};
-  }
+  if (n <= 8u) return median_in_regs<8>(Y, it, i, u, nmask, logN, g, n);
+  if (n <= uint32_t(kRegRounds)) return median_in_regs<kRegRounds>(Y, it, i, u, nmask, logN, g, n);
   // more rounds than registers: order statistics by counting ranks
   const uint32_t lo = (n - 1) / 2, hi = n / 2;
   R lr = 0, hr = 0, li = 0, hi_ = 0;
@@ -765,20 +773,38 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
     const R thr = thr_noise > thr_floor ? thr_noise : thr_floor;
 
     // ---- location, verification, median estimation ----
-    for (uint32_t i = tid; i < B; i += NT) {
-      uint32_t uo = kNone;
-      const R p = p0[i];
-      if (cand_u[i] && p >= thr && p > R(0)) {
-        uint32_t dd = 0;
-        const uint32_t u = locate_bucket<R>(pd, it, Y, i, &dd);
-        const R g = u != kNone ? ghat[dd] : R(0);
-        if (u != kNone && g != R(0)) {
-          cand_v[i] = median_estimate<R>(Y, it, i, u, nmask, logN, g);
-          cand_d[i] = dd;
-          uo = u;
-        }
+    // The buckets that pass the screen are listed first (in bucket order, a
+    // contiguous chunk per thread), so that the long location chains run on
+    // full wavefronts instead of on the few lanes whose bucket is active.
+    uint32_t* act = reinterpret_cast<uint32_t*>(scr);  // the median keys are no longer needed
+    uint32_t nact;
+    {
+      const uint32_t chunk = (B + NT - 1) / NT;
+      const uint32_t lo = min(B, tid * chunk), hi = min(B, lo + chunk);
+      uint32_t mine = 0;
+      for (uint32_t i = lo; i < hi; ++i) {
+        const R p = p0[i];
+        mine += (cand_u[i] && p >= thr && p > R(0)) ? 1u : 0u;
       }
-      cand_u[i] = uo;
+      uint32_t at = block_excl_scan(mine, wsum, &nact);
+      for (uint32_t i = lo; i < hi; ++i) {
+        const R p = p0[i];
+        if (cand_u[i] && p >= thr && p > R(0)) act[at++] = i;
+      }
+      __syncthreads();
+      for (uint32_t i = lo; i < hi; ++i) cand_u[i] = kNone;
+      __syncthreads();
+    }
+    for (uint32_t a = tid; a < nact; a += NT) {
+      const uint32_t i = act[a];
+      uint32_t dd = 0;
+      const uint32_t u = locate_bucket<R>(pd, it, Y, i, &dd);
+      const R g = u != kNone ? ghat[dd] : R(0);
+      if (u != kNone && g != R(0)) {
+        cand_v[i] = median_estimate<R>(Y, it, i, u, nmask, logN, g);
+        cand_d[i] = dd;
+        cand_u[i] = u;
+      }
     }
     __syncthreads();
 
