@@ -135,7 +135,7 @@ def main():
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the sparse FFT hot path is built and measured on a single "
-              "MI355X (signals of a batch are independent; see the sharding notes in DESIGN.md).",
+              "MI355X (signals of a batch are independent: several GPUs would each take a slice of the batch).",
               file=sys.stderr)
         sys.exit(2)
 

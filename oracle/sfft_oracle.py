@@ -23,9 +23,13 @@ in the design notes):
   * Location (Sec. 3.2): extended first region L + 2e (e = window transition
     half-width), integer schedule tau_j = floor(N / len_j), rational block
     centres, floor for the region start, a final enumeration step.
-  * Detection, verification and dedupe rules are this build's (the paper
+  * Detection, verification and dedupe rules are readings of their own (the paper
     assumes isolated buckets).
   * Estimation takes the median over the R+1 rounds of one iteration.
+  * The two-round location of sFFT3.0, which the paper sets against sFFT4.0
+    (Sec. 1, Sec. 3.1: R_m = 2 rounds), is read as offsets tau0 and tau0 + 1
+    and the phase-to-position conversion u = round(theta N / 2 pi) mod N
+    (Eq. 16 with tau = 1), then the same verification and estimation.
 """
 
 from __future__ import annotations
@@ -42,12 +46,12 @@ __all__ = [
     "location_schedule", "hash_to_bins", "subtract", "detect", "locate",
     "verify", "estimate", "sfft", "circ_dist", "samples_per_signal",
     "window_spectrum", "bucket_range", "phases", "multiscale_upper_bound",
-    "extension_lower_bound",
+    "extension_lower_bound", "BLK", "ENUM", "DIRECT",
 ]
 
 TWO_PI = 2.0 * math.pi
 MASK64 = (1 << 64) - 1
-BLK, ENUM = 0, 1
+BLK, ENUM, DIRECT = 0, 1, 2
 
 
 # --------------------------------------------------------------------------
@@ -191,10 +195,14 @@ class Plan:
     iters: list = field(default_factory=list)
 
 
-def make_plan(N, K, B, w, loops, l, q, delta=1e-6, seed=0, b_min=16, eta=1e-4, rho=0.25) -> Plan:
+def make_plan(N, K, B, w, loops, l, q, delta=1e-6, seed=0, b_min=16, eta=1e-4, rho=0.25,
+              location="multiscale") -> Plan:
     """Per-iteration parameters: B_m = max(B >> (m-1), b_min) buckets (the
     paper halves B per iteration), w_m = floor(w B_m / B) | 1 taps, a fresh
-    odd sigma_m and offset tau0_m per iteration from SplitMix64(seed)."""
+    odd sigma_m and offset tau0_m per iteration from SplitMix64(seed).
+    location = "multiscale" (sFFT4.0, Sec. 3.2) or "direct" (the two-round
+    location of sFFT3.0: one step with tau_1 = 1)."""
+    assert location in ("multiscale", "direct")
     assert N & (N - 1) == 0 and B & (B - 1) == 0
     q = Fraction(q)
     if w % 2 == 0:
@@ -208,7 +216,10 @@ def make_plan(N, K, B, w, loops, l, q, delta=1e-6, seed=0, b_min=16, eta=1e-4, r
         G, info = flat_window(N, Bm, wm, delta)
         e = info["e"]
         Ghat = window_spectrum(N, G, Lm // 2 + e)
-        lens, taus, kinds = location_schedule(N, Lm, e, l, q)
+        if location == "direct":
+            lens, taus, kinds = [0, Lm + 2 * e], [0, 1], [BLK, DIRECT]
+        else:
+            lens, taus, kinds = location_schedule(N, Lm, e, l, q)
         R = len(lens) - 1
         sigma = 2 * (rng.next() % (N // 2)) + 1
         tau0 = rng.next() % N
@@ -315,6 +326,9 @@ def locate(theta: list, i: int, it: Iteration, N: int, l: int, q: Fraction) -> i
     the single position of the region whose phase is closest (smallest
     position on a tie).  Returns u in [0, N)."""
     L, e = it.L, it.e
+    if it.kinds[1] == DIRECT:
+        # theta_1 = 2 pi u / N: the nearest position, halves rounded up
+        return math.floor(theta[1] * N / TWO_PI + 0.5) % N
     a = i * L - L // 2 - e
     qn, qd = q.numerator, q.denominator
     M2 = 2 * l * N

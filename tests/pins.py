@@ -271,6 +271,40 @@ def check_p7_location(O, N=4096, B=64, lq=((16, Fraction(1)), (4, Fraction(1, 4)
             assert O.locate(O.phases(yh, i), i, it2, N, l, q) == u
 
 
+def check_p12_direct_location(O, N=4096, B=64, delta=1e-8, seed=5, us=None):
+    """P12 (the two-round location of sFFT3.0, Eq. 16 with tau = 1): the plan
+    has one location step with offsets tau0 and tau0 + 1; a lone noiseless
+    coefficient is located exactly at every permuted position u from every
+    bucket that reaches it, and verification accepts it.  For phases off the
+    grid the located position is the nearest position by brute force over
+    all N (checked away from exact halves)."""
+    w = (B * int(math.log2(N))) | 1
+    P = O.make_plan(N, 1, B, w, 1, 16, 1, delta, seed=seed, location="direct")
+    it = P.iters[0]
+    assert it.R == 1 and it.taus[1] == 1 and it.kinds[1] == O.DIRECT
+    assert it.T[1] == (it.T[0] + 1) % N
+    v = complex(-0.28, 0.96)
+    for u in (range(N) if us is None else us):
+        for i_unwrapped in O.bucket_range(u, it.L, it.D):
+            i = i_unwrapped % B
+            yh = np.zeros((2, B), dtype=complex)
+            yh[:, i] = _single_tone_yhat(it, u, v, N, i)
+            th = O.phases(yh, i)
+            got = O.locate(th, i, it, N, 16, Fraction(1))
+            assert got == u, f"P12 u={u} bucket {i}: located {got}"
+            assert O.verify(th, u, i, it, N, 16), f"P12 verify rejected u={u} in bucket {i}"
+    r = rng(seed)
+    grid = 2 * math.pi * np.arange(N) / N
+    for _ in range(200):
+        frac = r.uniform(-0.49, 0.49)
+        c = int(r.integers(N))
+        theta = (2 * math.pi * (c + frac) / N) % (2 * math.pi)
+        d = np.abs(((grid - theta) + math.pi) % (2 * math.pi) - math.pi)
+        best = int(np.argmin(d))
+        th = [0.0, theta]
+        assert O.locate(th, 0, it, N, 16, Fraction(1)) == best == c % N
+
+
 def check_p8_estimate(O, N=4096, B=64, delta=1e-8, seed=9, n=200):
     """P8 (Eq. 14 with the median over rounds): a lone coefficient's value
     comes back from any bucket that holds it."""
@@ -307,13 +341,13 @@ def check_p8b_median_rule(O):
         assert abs(got - v) < 1e-9 * abs(v) or (it.R + 1) % 2 == 0
 
 
-def check_p9_end_to_end(O, cases, make_signal):
+def check_p9_end_to_end(O, cases, make_signal, location="multiscale"):
     """P9: an exactly K-sparse planted signal comes back: the support equals
     the planted support and values are within 10 K delta of the truth;
     Parseval N sum |v|^2 = sum |x|^2 holds to 1e-6."""
     for (N, K, B, w, M, l, q, delta, sseed, pseed) in cases:
         x, sup, vals = make_signal(N, K, sseed)
-        P = O.make_plan(N, K, B, w, M, l, q, delta, seed=pseed)
+        P = O.make_plan(N, K, B, w, M, l, q, delta, seed=pseed, location=location)
         idx, val, info = O.sfft(x, P)
         assert np.array_equal(idx, np.sort(sup)), f"P9 support mismatch at N={N}, K={K}, (l,q)=({l},{q})"
         truth = dict(zip(sup.tolist(), vals))

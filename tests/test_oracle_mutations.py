@@ -54,6 +54,7 @@ CHECKS = {
     "sched": pins.check_schedule,
     "rng": pins.check_splitmix64,
     "p11": pins.check_p11_detect,
+    "p12": lambda O: pins.check_p12_direct_location(O, us=range(0, 4096, 5)),
 }
 
 MUTANTS = [
@@ -112,6 +113,11 @@ MUTANTS = [
      "T = [tau0] + [(taus[j]) % N for j in range(1, R + 1)]", ["p9"]),
     # RNG: wrong mixing constant
     ("0xBF58476D1CE4E5B9", "0xBF58476D1CE4E5B8", ["rng"]),
+    # direct location: truncation instead of rounding
+    ("return math.floor(theta[1] * N / TWO_PI + 0.5) % N", "return math.floor(theta[1] * N / TWO_PI) % N", ["p12"]),
+    # direct location: the offset of the second round
+    ("lens, taus, kinds = [0, Lm + 2 * e], [0, 1], [BLK, DIRECT]",
+     "lens, taus, kinds = [0, Lm + 2 * e], [0, 2], [BLK, DIRECT]", ["p12"]),
 ]
 
 

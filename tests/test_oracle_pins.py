@@ -121,3 +121,13 @@ def test_top_k_ties_and_order():
     P = O.make_plan(N, K, 64, (64 * 12) | 1, 6, 16, 1, 1e-8, seed=12)
     idx, val, _ = O.sfft(x, P)
     assert idx.tolist() == [50, 100, 3000]
+
+
+def test_p12_direct_location_exhaustive():
+    pins.check_p12_direct_location(O)
+
+
+def test_p12_direct_end_to_end():
+    cases = [(2 ** 14, 50, 512, 7169, 8, 16, Fraction(1), 1e-8, 121, 122),
+             (2 ** 16, 300, 2048, 32769, 10, 16, Fraction(1), 1e-6, 123, 124)]
+    pins.check_p9_end_to_end(O, cases, _signal, location="direct")
