@@ -389,6 +389,30 @@ def main():
                 "support_agreement_f16_vs_f32": round(float(np.min(agree)), 4),
                 "max_rel_l2_f16_vs_f32_common": worst}
 
+    def direct_form(steps):
+        """The same batch and plan parameters with the two-round direct location
+        (sFFT3.0 reading: one step with tau = 1 instead of the multiscale
+        schedule), position-major; recall against the planted supports."""
+        from paper_2011_05698_amd.signals import planted_spectrum
+
+        pdir = sfft.Plan(N, K, B, w, M, l, q, delta=delta, seed=plan_seed, location="direct")
+        bd = sfft.InterleavedBatch(pdir, n)
+        od = bd.outputs(dev)
+        r = time_batch(bd, lambda: bd.execute(XT, scales=scales, outs=od), steps, "direct location", True)
+        bd.close()
+        rec = []
+        for s_ in range(8):
+            sup, _ = planted_spectrum(N, K, sig_seed + s_)
+            c = int(od[2][s_].item())
+            rec.append(len(np.intersect1d(od[0][s_, :c].cpu().numpy(), sup)) / K)
+        return {"location": "two rounds, u = round(theta N / 2 pi)", "layout": "position-major",
+                "samples_per_signal": pdir.samples, "signals_per_s": round(r["value"], 1),
+                "ms_per_step": round(r["ms_per_step"], 4),
+                "stage_ms": {"fold": round(r["stage_ms"][0], 4), "bucket_fft": round(r["stage_ms"][1], 4),
+                             "recover": round(r["stage_ms"][2], 4)},
+                "recall_first_8": round(float(np.mean(rec)), 4),
+                "note": "K/B = 0.49 here: two rounds cannot screen collisions as the multiscale rounds do"}
+
     main_res = run_layout(args.layout, args.steps)
     context = None
     if not args.no_context:
@@ -403,6 +427,8 @@ def main():
     if not args.no_forms and dt == "c64":
         forms["precision"], form_outs["precision"] = precision_form(max(2, args.steps // 2))
         forms["batching"], form_outs["batching"] = batching_form(max(2, args.steps // 2))
+    if not args.no_forms and dt == "c64":
+        forms["direct_location"] = direct_form(max(2, args.steps // 2))
     if args.large_form:
         forms["large_precision"] = large_form(args.large_form, max(2, args.steps // 2))
 

@@ -58,6 +58,16 @@ typedef struct sfft_batch_s* sfft_batch_t;
 #define SFFT_PLAN_HOST_ONLY 1u   /* build host tables only; no device memory, no execute */
 
 /* Optional plan settings; pass NULL to sfft_plan for the defaults below. */
+/* How an iteration locates the lone coefficient of a bucket:
+ *   SFFT_LOCATE_MULTISCALE -- sFFT4.0 (Sec. 3.2): block by block over R
+ *       rounds with multipliers tau_j = floor(N / len_j), a final enumeration;
+ *   SFFT_LOCATE_DIRECT -- the two-round location of sFFT3.0 that the paper
+ *       sets sFFT4.0 against (Sec. 1, Sec. 3.1: R_m = 2 rounds): offsets tau0
+ *       and tau0 + 1, u = round(theta N / 2 pi) mod N (Eq. 16 with tau = 1);
+ *       theta in FP64 at N >= 2^24.  Faster, and less robust to collisions
+ *       and noise.  Verification and estimation are the same for both. */
+typedef enum { SFFT_LOCATE_MULTISCALE = 0, SFFT_LOCATE_DIRECT = 1 } sfft_location;
+
 typedef struct {
   double delta;     /* window leakage / truncation level, 0 < delta < 0.1 (default 1e-6)   */
   uint64_t seed;    /* SplitMix64 seed of the per-iteration sigma, tau0 draws (default 0)  */
@@ -68,7 +78,7 @@ typedef struct {
   double eta;       /* detection floor relative to the strongest bucket (default 1e-4)     */
   double rho;       /* round-to-round magnitude tolerance of a lone bucket (default 0.25)  */
   uint32_t flags;   /* SFFT_PLAN_* bits                                                     */
-  uint32_t pad1;
+  uint32_t location; /* sfft_location (default SFFT_LOCATE_MULTISCALE)                      */
 } sfft_options;
 
 /* Fills *opt with the defaults. */
@@ -164,7 +174,8 @@ typedef struct {
   uint64_t sigma, sigma_inv, tau0;
   int64_t y_offset;      /* complex-element offset of this iteration in the yhat layout */
   int64_t T[48], tau[48], len[48];
-  int32_t last_is_enum;  /* always 1: the last step enumerates positions */
+  int32_t last_kind;     /* 1: the last step enumerates positions (multiscale),
+                            2: direct phase-to-position conversion (two-round)  */
   int32_t pad;
 } sfft_iter_info;
 sfft_status sfft_get_iter_info(sfft_plan_t p, int32_t m, sfft_iter_info* info);

@@ -324,7 +324,7 @@ sfft_status sfft_get_iter_info(sfft_plan_t p, int32_t m, sfft_iter_info* info) {
     info->tau[j] = it.d.tau[j];
     info->len[j] = it.d.len[j];
   }
-  info->last_is_enum = 1;
+  info->last_kind = p->hp.desc.location == SFFT_LOCATE_DIRECT ? 2 : 1;
   return SFFT_OK;
 }
 

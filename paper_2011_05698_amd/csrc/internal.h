@@ -45,6 +45,8 @@ struct PlanDesc {
   uint32_t sort_cap;              // power of two >= max(rec_cap, Bmax)
   uint32_t fp64_phase;            // take location phases in FP64 (N >= 2^24)
   uint32_t log_hcap;              // hash index of the store: 2^log_hcap >= 2 rec_cap slots
+  uint32_t location;              // sfft_location of every iteration
+  uint32_t pad_loc;
   uint64_t y_total;               // complex elements of bucket values per signal
   uint64_t ws_bytes;              // workspace bytes per signal
   // byte offsets inside one signal's workspace

@@ -148,6 +148,9 @@ sfft_status build_host_plan(HostPlan& hp, int64_t N, int64_t K, int64_t B, int64
   if (opt.dtype < 0 || opt.dtype > 2) return bad(SFFT_ERR_PARAM, "unknown dtype");
   if (!is_pow2(opt.b_min) || opt.b_min < 16 || opt.b_min > B) return bad(SFFT_ERR_PARAM, "b_min must be a power of two with 16 <= b_min <= B");
   if (!(opt.eta >= 0.0 && opt.eta < 1.0) || !(opt.rho > 0.0)) return bad(SFFT_ERR_PARAM, "need 0 <= eta < 1 and rho > 0");
+  if (opt.location != SFFT_LOCATE_MULTISCALE && opt.location != SFFT_LOCATE_DIRECT)
+    return bad(SFFT_ERR_PARAM, "unknown location method");
+  const bool direct = opt.location == SFFT_LOCATE_DIRECT;
   const int64_t bmax = opt.dtype == SFFT_C128 ? kMaxBucketsF64 : kMaxBucketsF32;
   if (B > bmax) return bad(SFFT_ERR_UNSUPPORTED, "B above the bucket-FFT limit of this dtype");
 
@@ -190,11 +193,18 @@ sfft_status build_host_plan(HostPlan& hp, int64_t N, int64_t K, int64_t B, int64
     d.log_B = std::log(double(Bm));
 
     // Location schedule (Sec. 3.2): extended first region, shrink by (1+q)/l.
+    // The two-round location has a single step with tau = 1.
     it.kinds.assign(1, 0);
     int64_t len = Lm + 2 * e;
     int R = 0;
     d.tau[0] = 0; d.len[0] = 0;
-    while (true) {
+    if (direct) {
+      R = 1;
+      d.len[1] = uint32_t(len);
+      d.tau[1] = 1;
+      it.kinds.push_back(2);
+    }
+    while (!direct) {
       ++R;
       if (R >= kMaxRounds) return bad(SFFT_ERR_UNSUPPORTED, "location needs more than 47 steps for these (l, q)");
       int64_t num = (qd + qn) * len, den = qd * int64_t(l);
@@ -230,6 +240,7 @@ sfft_status build_host_plan(HostPlan& hp, int64_t N, int64_t K, int64_t B, int64
 
   PlanDesc& pd = hp.desc;
   std::memset(&pd, 0, sizeof(pd));
+  pd.location = opt.location;
   pd.N = uint32_t(N); pd.logN = uint32_t(ilog2(N)); pd.K = uint32_t(K); pd.M = uint32_t(loops);
   pd.l = uint32_t(l); pd.logl = uint32_t(ilog2(l));
   pd.qn = int32_t(qn); pd.logqd = uint32_t(ilog2(qd));

@@ -308,7 +308,13 @@ __device__ uint32_t locate_bucket(const PlanDesc* pd, const IterDesc* it, const 
   const int64_t qd = int64_t(1) << pd->logqd, qn = pd->qn;
   int64_t a = int64_t(i) * L - int64_t(L / 2) - int64_t(it->e);
   uint32_t u = 0;
-  for (uint32_t j = 1; j <= R_; ++j) {
+  if (pd->location == SFFT_LOCATE_DIRECT) {
+    // two rounds, tau_1 = 1: theta_1 = 2 pi u / N; the nearest position,
+    // halves rounded up (floor(2 theta N) + 1) / 2 on the binary angle
+    const uint64_t th = theta_bin(y0, Y[size_t(B) + i], fp64);
+    u = uint32_t(((th >> (63 - logN)) + 1) >> 1) & nmask;
+  }
+  for (uint32_t j = 1; j <= R_ && pd->location != SFFT_LOCATE_DIRECT; ++j) {
     const uint64_t th = theta_bin(y0, Y[size_t(j) * B + i], fp64);
     const uint64_t len = it->len[j], tau = it->tau[j];
     if (j < R_) {

@@ -42,7 +42,7 @@ class Options(ctypes.Structure):
     _fields_ = [("delta", ctypes.c_double), ("seed", ctypes.c_uint64), ("dtype", ctypes.c_int32),
                 ("kahan", ctypes.c_int32), ("b_min", ctypes.c_int32), ("pad0", ctypes.c_int32),
                 ("eta", ctypes.c_double), ("rho", ctypes.c_double), ("flags", ctypes.c_uint32),
-                ("pad1", ctypes.c_uint32)]
+                ("location", ctypes.c_uint32)]
 
 
 class FoldConfig(ctypes.Structure):
@@ -63,7 +63,7 @@ class IterInfo(ctypes.Structure):
                 ("sigma", ctypes.c_uint64), ("sigma_inv", ctypes.c_uint64), ("tau0", ctypes.c_uint64),
                 ("y_offset", ctypes.c_int64), ("T", ctypes.c_int64 * MAX_ROUNDS),
                 ("tau", ctypes.c_int64 * MAX_ROUNDS), ("len", ctypes.c_int64 * MAX_ROUNDS),
-                ("last_is_enum", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("last_kind", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 def _hip_runtimes():
@@ -256,11 +256,12 @@ class Plan:
     """A plan for signals of length N (see sfft_plan in include/sfft.h)."""
 
     def __init__(self, N, K, B, w, loops, multiscale, extension, *, delta=1e-6, seed=0, dtype="c64",
-                 kahan=False, b_min=16, eta=1e-4, rho=0.25, host_only=False):
+                 kahan=False, b_min=16, eta=1e-4, rho=0.25, host_only=False, location="multiscale"):
         o = sfft_default_options()
         o.delta, o.seed, o.dtype, o.kahan, o.b_min = delta, seed, DTYPES[dtype], int(kahan), b_min
         o.eta, o.rho = eta, rho
         o.flags = SFFT_PLAN_HOST_ONLY if host_only else 0
+        o.location = {"multiscale": 0, "direct": 1}[location]
         self.dtype = dtype
         self.handle = sfft_plan(N, K, B, w, loops, multiscale, float(Fraction(extension)), o)
         i = sfft_get_plan_info(self.handle)
@@ -284,7 +285,8 @@ class Plan:
         R = it.R
         return dict(B=it.B, L=it.L, w=it.w, h=it.h, e=it.e, R=R, d_delta=it.d_delta, sigma=it.sigma,
                     sigma_inv=it.sigma_inv, tau0=it.tau0, y_offset=it.y_offset,
-                    T=list(it.T[:R + 1]), tau=list(it.tau[:R + 1]), len=list(it.len[:R + 1]))
+                    T=list(it.T[:R + 1]), tau=list(it.tau[:R + 1]), len=list(it.len[:R + 1]),
+                    last_kind=it.last_kind)
 
     def tables(self, m):
         it = self.iteration(m)

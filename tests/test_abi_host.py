@@ -45,11 +45,12 @@ PLANS = [
 ]
 
 
+@pytest.mark.parametrize("location", ["multiscale", "direct"])
 @pytest.mark.parametrize("case", PLANS, ids=lambda c: f"N{c[0]}_B{c[2]}_l{c[5]}_q{c[6]}")
-def test_plan_matches_oracle(case):
+def test_plan_matches_oracle(case, location):
     N, K, B, w, M, l, q, delta, seed = case
-    P = O.make_plan(N, K, B, w, M, l, q, delta, seed=seed)
-    p = sfft.Plan(N, K, B, w, M, l, q, delta=delta, seed=seed, host_only=True)
+    P = O.make_plan(N, K, B, w, M, l, q, delta, seed=seed, location=location)
+    p = sfft.Plan(N, K, B, w, M, l, q, delta=delta, seed=seed, host_only=True, location=location)
     assert p.samples == O.samples_per_signal(P)
     off = 0
     for m, it in enumerate(P.iters):
@@ -59,6 +60,7 @@ def test_plan_matches_oracle(case):
         assert g["T"] == it.T
         assert g["tau"][1:] == it.taus[1:] and g["len"][1:] == it.lens[1:]
         assert g["y_offset"] == off
+        assert g["last_kind"] == it.kinds[-1]  # 1: enumeration, 2: direct conversion
         off += (it.R + 1) * it.B
         assert abs(g["d_delta"] - it.d_delta) <= 1e-9 * it.d_delta
         G, Ghat = p.tables(m)

@@ -235,6 +235,34 @@ def test_large_bucket_count_f16(sf, snr, mags):
         assert rel_l2(np.array([gi[f] for f in common]), np.array([oi[f] for f in common])) <= 1e-3
 
 
+DIRECT = [
+    # N, K, B, w, loops, delta, storage, signal seed, plan seed
+    (2 ** 14, 50, 512, 7169, 8, 1e-8, "c64", 121, 122),
+    (2 ** 14, 50, 512, 7169, 8, 1e-8, "c128", 121, 122),
+    (2 ** 16, 300, 2048, 32769, 10, 1e-6, "c64", 123, 124),
+    (2 ** 24, 1000, 8192, 196609, 10, 1e-6, "c64", 131, 132),  # theta in FP64 (N >= 2^24)
+]
+
+
+@pytest.mark.parametrize("case", DIRECT, ids=lambda c: f"N{c[0]}_K{c[1]}_B{c[2]}_{c[6]}")
+def test_direct_location_parity(sf, case):
+    """The two-round direct location (u = round(theta N / 2 pi)): on exactly
+    K-sparse signals with few collisions the planted support comes back, the
+    GPU path matches the oracle's support bit for bit and its values within
+    1e-4 (1e-10 in complex128)."""
+    N, K, B, w, M, delta, dt, ss, ps = case
+    x, sup, _ = make_signal(SignalSpec(N, K, ss))
+    xd, scale, xq = to_dev(x, dt)
+    P = O.make_plan(N, K, B, w, M, 16, 1, delta, seed=ps, location="direct")
+    oidx, oval, _ = O.sfft(xq, P)
+    plan = sf.Plan(N, K, B, w, M, 16, 1.0, delta=delta, seed=ps, dtype=dt, location="direct")
+    assert plan.iteration(0)["R"] == 1 and plan.iteration(0)["last_kind"] == 2
+    gidx, gval, c = run_gpu(sf, plan, xd, scale)
+    assert np.array_equal(oidx, np.sort(sup))
+    assert np.array_equal(gidx, oidx)
+    assert rel_l2(gval, oval) <= (1e-10 if dt == "c128" else 1e-4)
+
+
 def test_batch_uneven_matches_single(sf):
     """Signals of different N and K in one batch give exactly what single
     executes give, and match the oracle."""
