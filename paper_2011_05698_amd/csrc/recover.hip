@@ -20,6 +20,7 @@ constexpr int kLdsBytes = 75776;    // one buffer, reused phase by phase; two wo
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr int kRegRounds = 16;      // rounds whose estimates are sorted in registers
 constexpr int kVgBatch = 4;         // entries whose loads a thread issues together
+constexpr int kMaxRoundsPerPass = 4; // rounds the subtraction handles in one pass when LDS allows
 
 struct K128 {
   uint64_t hi, lo;
@@ -570,19 +571,32 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
     const uint32_t o_sv = (o_sk + nrec * 8u + 15u) & ~15u;
     const uint32_t o_gq = (o_sv + nrec * CB + 15u) & ~15u;
     const uint32_t o_w = (o_gq + nrec * nslot * uint32_t(sizeof(R)) + 15u) & ~15u;
-    const uint32_t o_run = (o_w + nrec * CB + 15u) & ~15u;  // per bucket: first entry and length of its run
-    const uint32_t o_ys = o_run + B * 8u;                   // one round's sums (bucket values in the workspace)
-    const uint32_t sub_lds_y = nrec == 0 ? 0u : o_ys;       // with the bucket block staged in LDS
-    const uint32_t sub_ws_y = nrec == 0 ? 0u : o_ys + B * CB;
+    // then per bucket the bounds of its run, and (bucket values in the
+    // workspace) the sums of the rounds of one pass; rp rounds share a pass
+    auto sub_bytes = [&](uint32_t rp, bool staged) -> uint32_t {
+      if (nrec == 0) return 0u;
+      const uint32_t orun = (o_w + nrec * CB * rp + 15u) & ~15u;
+      return orun + B * 8u + (staged ? 0u : B * CB * rp);
+    };
     const uint32_t det_need = B * uint32_t(sizeof(typename RK::T));
     const uint32_t ys_bytes = (R1 * B * uint32_t(sizeof(cplx<R>)) + 15u) & ~15u;
     const uint32_t pb_bytes = ((B * uint32_t(sizeof(R)) + 15u) & ~15u) + 2u * ((B * 4u + 15u) & ~15u) +
                               B * uint32_t(sizeof(cplx<R>));
-    const bool y_lds = ys_bytes + (sub_lds_y > det_need ? sub_lds_y : det_need) <= uint32_t(kLdsBytes);
-    const uint32_t sub_need = y_lds ? sub_lds_y : sub_ws_y;
+    auto fits = [&](uint32_t rp, bool staged, bool pbs) -> bool {
+      const uint32_t sub = sub_bytes(rp, staged);
+      return (staged ? ys_bytes : 0u) + (pbs ? pb_bytes : 0u) + (sub > det_need ? sub : det_need) <=
+             uint32_t(kLdsBytes);
+    };
+    const bool y_lds = fits(1, true, false);
+    const bool pb_lds_plan = fits(1, y_lds, true);
+    uint32_t rp = 1;  // more rounds per pass only where the LDS plan above still holds
+    while (rp < uint32_t(kMaxRoundsPerPass) && fits(rp * 2, y_lds, pb_lds_plan)) rp *= 2;
+    const uint32_t o_run = (o_w + nrec * CB * rp + 15u) & ~15u;
+    const uint32_t o_ys = o_run + B * 8u;
+    const uint32_t sub_need = sub_bytes(rp, y_lds);
     const uint32_t scr_need = sub_need > det_need ? sub_need : det_need;
     const uint32_t pb_at = y_lds ? ys_bytes : 0u;
-    const bool pb_lds = pb_at + pb_bytes + scr_need <= uint32_t(kLdsBytes);
+    const bool pb_lds = pb_lds_plan;
     const uint32_t scr_at = (pb_at + (pb_lds ? pb_bytes : 0u) + 15u) & ~15u;
     unsigned char* scr = lds_buf + scr_at;
     const uint32_t scr_bytes = uint32_t(kLdsBytes) - scr_at;
@@ -698,14 +712,20 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
       uint32_t S = 1;
       while (S < 64 && double(S) < mean_run && S * 2u * B <= NT) S <<= 1;
       const uint32_t team = tid / S, lane = tid & (S - 1), nteams = NT / S;
-      for (uint32_t j = 0; j < R1; ++j) {
-        const uint32_t Tj = it->T[j];
-        for (uint32_t q = tid; q < nrec; q += NT)
-          w[q] = cmul(sv[q], expi<R>((Tj * uint32_t(sk[q] >> 32)) & nmask, logN, R(-1)));
+      for (uint32_t j0 = 0; j0 < R1; j0 += rp) {
+        const uint32_t nj = min(rp, R1 - j0);
+        for (uint32_t q = tid; q < nrec; q += NT) {
+          const uint32_t u = uint32_t(sk[q] >> 32);
+          const cplx<R> v = sv[q];
+          for (uint32_t r = 0; r < nj; ++r)
+            w[q * rp + r] = cmul(v, expi<R>((it->T[j0 + r] * u) & nmask, logN, R(-1)));
+        }
         __syncthreads();
         for (uint32_t base_i = 0; base_i < B; base_i += nteams) {  // uniform trip count per wave
           const uint32_t i = base_i + team;
-          cplx<R> acc{0, 0};
+          cplx<R> acc[kMaxRoundsPerPass];
+#pragma unroll
+          for (int r = 0; r < kMaxRoundsPerPass; ++r) acc[r] = cplx<R>{0, 0};
           if (i < B) {
             const RunBounds rb = run[i];
             const uint32_t q0 = rb.first, cnt = rb.count;
@@ -714,31 +734,48 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
               q = q >= nrec ? q - nrec : q;
               const uint32_t u = uint32_t(sk[q] >> 32);
               const uint32_t slot = (i - uint32_t(first_bucket(u, D, it->logL))) & (B - 1);
-              acc = cadd(acc, cscale(w[q], gq[q * nslot + slot]));
+              const R g = gq[q * nslot + slot];
+#pragma unroll
+              for (int r = 0; r < kMaxRoundsPerPass; ++r)
+                if (uint32_t(r) < nj) acc[r] = cadd(acc[r], cscale(w[q * rp + uint32_t(r)], g));
             }
           }
-          acc.re = team_sum(acc.re, S);  // the team's sum lands in its last lane
-          acc.im = team_sum(acc.im, S);
+#pragma unroll
+          for (int r = 0; r < kMaxRoundsPerPass; ++r) {
+            if (uint32_t(r) < nj) {  // uniform; the team's sums land in its last lane
+              acc[r].re = team_sum(acc[r].re, S);
+              acc[r].im = team_sum(acc[r].im, S);
+            }
+          }
           if (i < B && lane == S - 1) {
-            if (y_lds) Y[size_t(j) * B + i] = csub(Y[size_t(j) * B + i], acc);  // staged block: in place
-            else ysub[i] = acc;
+#pragma unroll
+            for (int r = 0; r < kMaxRoundsPerPass; ++r) {
+              if (uint32_t(r) < nj) {
+                cplx<R>* yp = Y + size_t(j0 + uint32_t(r)) * B + i;
+                if (y_lds) *yp = csub(*yp, acc[r]);  // staged block: in place
+                else ysub[size_t(r) * B + i] = acc[r];
+              }
+            }
           }
         }
         __syncthreads();
         if (y_lds) continue;
-        // bucket values in the workspace: take the round's sums off, loads batched
-        cplx<R>* Yj = Y + size_t(j) * B;
-        for (uint32_t ib = 0; ib < B; ib += kVgBatch * NT) {
-          cplx<R> yv[kVgBatch];
+        // bucket values in the workspace: take the pass's sums off, loads batched
+        for (uint32_t r = 0; r < nj; ++r) {
+          cplx<R>* Yj = Y + size_t(j0 + r) * B;
+          const cplx<R>* sj = ysub + size_t(r) * B;
+          for (uint32_t ib = 0; ib < B; ib += kVgBatch * NT) {
+            cplx<R> yv[kVgBatch];
 #pragma unroll
-          for (int e = 0; e < kVgBatch; ++e) {
-            const uint32_t i = ib + uint32_t(e) * NT + tid;
-            if (i < B) yv[e] = Yj[i];
-          }
+            for (int e = 0; e < kVgBatch; ++e) {
+              const uint32_t i = ib + uint32_t(e) * NT + tid;
+              if (i < B) yv[e] = Yj[i];
+            }
 #pragma unroll
-          for (int e = 0; e < kVgBatch; ++e) {
-            const uint32_t i = ib + uint32_t(e) * NT + tid;
-            if (i < B) Yj[i] = csub(yv[e], ysub[i]);
+            for (int e = 0; e < kVgBatch; ++e) {
+              const uint32_t i = ib + uint32_t(e) * NT + tid;
+              if (i < B) Yj[i] = csub(yv[e], sj[i]);
+            }
           }
         }
         __syncthreads();

@@ -414,6 +414,56 @@ def test_position_major_metric_shape(sf):
         assert rel_l2(val[s, :c].cpu().numpy().astype(np.complex128), oval) <= 1e-4
 
 
+SMALLEST = [
+    # N, K, B, w, loops, signal seed: the smallest plans the ABI accepts (B = 16 >= b_min, B <= N/4)
+    (64, 1, 16, 33, 3, 32),
+    (256, 2, 16, 129, 4, 31),
+    (1024, 8, 64, 641, 6, 33),
+]
+
+
+@pytest.mark.parametrize("case", SMALLEST, ids=lambda c: f"N{c[0]}_K{c[1]}_B{c[2]}")
+def test_smallest_plans(sf, case):
+    N, K, B, w, M, ss = case
+    x, sup, _ = make_signal(SignalSpec(N, K, ss))
+    xd, scale, xq = to_dev(x, "c64")
+    P = O.make_plan(N, K, B, w, M, 16, 1, 1e-6, seed=ss + 1)
+    oidx, oval, _ = O.sfft(xq, P)
+    plan = sf.Plan(N, K, B, w, M, 16, 1.0, delta=1e-6, seed=ss + 1)
+    gidx, gval, c = run_gpu(sf, plan, xd, scale)
+    assert np.array_equal(oidx, np.sort(sup))
+    assert np.array_equal(gidx, oidx)
+    assert rel_l2(gval, oval) <= 1e-4
+
+
+def test_largest_signal_length(sf):
+    """N = 2^30, the largest length a plan accepts: four tones synthesized on
+    the device with exact integer phases (f n mod N).  The oracle cannot run
+    at this size; the answer is known in closed form: the support is the four
+    frequencies and the values are the amplitudes (Eq. 2 normalization)."""
+    N, K, B, M = 2 ** 30, 4, 1024, 4
+    w = (B * 30) | 1
+    freqs = [1, 123456789, 2 ** 29 + 7, N - 3]
+    amps = [0.6 - 0.8j, -1.0 + 0.0j, 0.28 + 0.96j, 0.8 + 0.6j]
+    x = torch.zeros(N, dtype=torch.complex64, device=DEV)
+    step = 2 ** 27
+    for c0 in range(0, N, step):  # chunks keep the float64 temporaries small
+        n = torch.arange(c0, c0 + step, dtype=torch.int64, device=DEV)
+        acc = torch.zeros(step, dtype=torch.complex128, device=DEV)
+        for f, a in zip(freqs, amps):
+            ph = ((n * f) % N).to(torch.float64) * (2.0 * math.pi / N)
+            acc += a * torch.polar(torch.ones_like(ph), ph)
+        x[c0:c0 + step] = acc.to(torch.complex64)
+        del n, acc
+    plan = sf.Plan(N, K, B, w, M, 16, 1.0, delta=1e-6, seed=77)
+    gidx, gval, c = run_gpu(sf, plan, x, 1.0)
+    order = np.argsort(freqs)
+    assert np.array_equal(gidx, np.array(freqs)[order])
+    assert rel_l2(gval, np.array(amps)[order]) <= 1e-4
+    del x
+    torch.cuda.empty_cache()
+
+
 def test_edge_cases(sf):
     N, B = 2 ** 12, 64
     plan = sf.Plan(N, 3, B, (B * 12) | 1, 6, 16, 1.0, delta=1e-8, seed=4)
