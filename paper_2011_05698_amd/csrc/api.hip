@@ -26,8 +26,9 @@ struct sfft_plan_s {
   PlanDesc* d_plan = nullptr;
   FoldTile* d_tiles = nullptr;
   RoundItem* d_items = nullptr;
+  FftGroup* d_groups = nullptr;
   unsigned char* d_ws = nullptr;
-  uint32_t ntiles = 0, nitems = 0;
+  uint32_t ntiles = 0, nitems = 0, nfft = 0, fft_points = 0;
   FoldConfig fold{8, 0};
 };
 
@@ -38,9 +39,10 @@ struct sfft_batch_s {
   SignalDesc* d_sigs = nullptr;
   FoldTile* d_tiles = nullptr;
   RoundItem* d_items = nullptr;
+  FftGroup* d_groups = nullptr;
   unsigned char* d_ws = nullptr;
   std::vector<uint64_t> ws_off;
-  uint32_t ntiles = 0, nitems = 0, max_B = 0;
+  uint32_t ntiles = 0, nitems = 0, max_B = 0, nfft = 0, fft_points = 0;
   std::vector<SignalDesc> bound;    // host copy of the uploaded descriptor table
   bool has_binding = false;
   hipGraph_t graph = nullptr;
@@ -64,6 +66,25 @@ sfft_status hip_fail(hipError_t e, const char* what) {
 }
 
 uint64_t align256(uint64_t v) { return (v + 255) & ~uint64_t(255); }
+
+// Orders round items by B (largest first, stable) and cuts them into
+// bucket-DFT workgroups of equal B and at most kFftGroupPoints points.
+template <class BOf>
+void group_rounds(std::vector<RoundItem>& items, BOf b_of, std::vector<FftGroup>& groups, uint32_t& max_points) {
+  std::stable_sort(items.begin(), items.end(),
+                   [&](const RoundItem& x, const RoundItem& y) { return b_of(x) > b_of(y); });
+  groups.clear();
+  max_points = 0;
+  for (uint32_t a = 0; a < uint32_t(items.size());) {
+    const uint32_t B = b_of(items[a]);
+    const uint32_t cap = std::max<uint32_t>(1u, kFftGroupPoints / B);
+    uint32_t c = 1;
+    while (a + c < uint32_t(items.size()) && c < cap && b_of(items[a + c]) == B) ++c;
+    groups.push_back(FftGroup{a, c});
+    max_points = std::max(max_points, c * B);
+    a += c;
+  }
+}
 
 // Work lists of one signal, signal-major: the fold covers the (R_m+1) x B_m
 // (round, bucket) items of every iteration in tiles of kFoldTile items.
@@ -95,8 +116,11 @@ sfft_status upload_plan(sfft_plan_t p) {
   std::vector<FoldTile> tiles;
   std::vector<RoundItem> items;
   build_work_lists(hp, 0, tiles, items);
+  std::vector<FftGroup> groups;
+  group_rounds(items, [&](const RoundItem& r) { return hp.iters[r.m].d.B; }, groups, p->fft_points);
   p->ntiles = uint32_t(tiles.size());
   p->nitems = uint32_t(items.size());
+  p->nfft = uint32_t(groups.size());
 
   uint64_t off = 0;
   auto take = [&](uint64_t bytes) {
@@ -111,6 +135,7 @@ sfft_status upload_plan(sfft_plan_t p) {
   const uint64_t o_tw = take(ntw * 2 * rs);
   const uint64_t o_tiles = take(sizeof(FoldTile) * tiles.size());
   const uint64_t o_items = take(sizeof(RoundItem) * items.size());
+  const uint64_t o_groups = take(sizeof(FftGroup) * groups.size());
   const uint64_t o_ws = take(hp.desc.ws_bytes);
 
   hipError_t e = hipMalloc(&p->d_mem, off);
@@ -155,11 +180,13 @@ sfft_status upload_plan(sfft_plan_t p) {
   std::memcpy(host.data() + o_plan, &pd, sizeof(PlanDesc));
   std::memcpy(host.data() + o_tiles, tiles.data(), sizeof(FoldTile) * tiles.size());
   std::memcpy(host.data() + o_items, items.data(), sizeof(RoundItem) * items.size());
+  std::memcpy(host.data() + o_groups, groups.data(), sizeof(FftGroup) * groups.size());
   e = hipMemcpy(p->d_mem, host.data(), o_ws, hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy(plan tables)");
   p->d_plan = reinterpret_cast<PlanDesc*>(p->d_mem + o_plan);
   p->d_tiles = reinterpret_cast<FoldTile*>(p->d_mem + o_tiles);
   p->d_items = reinterpret_cast<RoundItem*>(p->d_mem + o_items);
+  p->d_groups = reinterpret_cast<FftGroup*>(p->d_mem + o_groups);
   p->d_ws = p->d_mem + o_ws;
   p->on_device = true;
   return SFFT_OK;
@@ -201,7 +228,7 @@ uint32_t max_B(const HostPlan& hp) {
 sfft_status run_hash(sfft_plan_t p, const SigArg& a, hipStream_t s) {
   int e = launch_fold(p->hp.dtype, p->hp.kahan, p->fold, a, p->d_tiles, p->ntiles, s);
   if (e != hipSuccess) return hip_fail(hipError_t(e), "fold launch");
-  e = launch_bucket_fft(p->hp.dtype, a, p->d_items, p->nitems, max_B(p->hp), s);
+  e = launch_bucket_fft(p->hp.dtype, a, p->d_items, p->d_groups, p->nfft, p->fft_points, s);
   if (e != hipSuccess) return hip_fail(hipError_t(e), "bucket FFT launch");
   return SFFT_OK;
 }
@@ -414,12 +441,16 @@ sfft_status create_batch(sfft_batch_t* out, const sfft_plan_t* h_plans, int32_t 
     tiles.clear();
     interleaved_tiles(h_plans[0]->hp, b->ngroups, tiles);
   }
+  std::vector<FftGroup> groups;
+  group_rounds(items, [&](const RoundItem& r) { return h_plans[r.sig]->hp.iters[r.m].d.B; }, groups, b->fft_points);
   b->ntiles = uint32_t(tiles.size());
   b->nitems = uint32_t(items.size());
+  b->nfft = uint32_t(groups.size());
   const uint64_t o_sigs = 0;
   const uint64_t o_tiles = align256(sizeof(SignalDesc) * n);
   const uint64_t o_items = o_tiles + align256(sizeof(FoldTile) * tiles.size());
-  const uint64_t o_ws = o_items + align256(sizeof(RoundItem) * items.size());
+  const uint64_t o_groups = o_items + align256(sizeof(RoundItem) * items.size());
+  const uint64_t o_ws = o_groups + align256(sizeof(FftGroup) * groups.size());
   hipError_t e = hipMalloc(&b->d_mem, o_ws + ws);
   if (e != hipSuccess) {
     delete b;
@@ -428,9 +459,11 @@ sfft_status create_batch(sfft_batch_t* out, const sfft_plan_t* h_plans, int32_t 
   b->d_sigs = reinterpret_cast<SignalDesc*>(b->d_mem + o_sigs);
   b->d_tiles = reinterpret_cast<FoldTile*>(b->d_mem + o_tiles);
   b->d_items = reinterpret_cast<RoundItem*>(b->d_mem + o_items);
+  b->d_groups = reinterpret_cast<FftGroup*>(b->d_mem + o_groups);
   b->d_ws = b->d_mem + o_ws;
   e = hipMemcpy(b->d_tiles, tiles.data(), sizeof(FoldTile) * tiles.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(b->d_items, items.data(), sizeof(RoundItem) * items.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(b->d_groups, groups.data(), sizeof(FftGroup) * groups.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking);
   if (e != hipSuccess) {
     (void)hipFree(b->d_mem);
@@ -464,7 +497,7 @@ sfft_status bind_and_replay(sfft_batch_t b, const std::vector<SignalDesc>& sig, 
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
     const SigArg a = table_arg(b);
     int le = launch_batch_fold(b, b->fold, cs);
-    if (le == hipSuccess) le = launch_bucket_fft(b->dtype, a, b->d_items, b->nitems, b->max_B, cs);
+    if (le == hipSuccess) le = launch_bucket_fft(b->dtype, a, b->d_items, b->d_groups, b->nfft, b->fft_points, cs);
     if (le == hipSuccess) le = launch_recover(b->dtype, a, uint32_t(n), cs);
     hipGraph_t g = nullptr;
     hipError_t ee = hipStreamEndCapture(cs, &g);
@@ -545,7 +578,7 @@ sfft_status sfft_batch_launch_stage(sfft_batch_t b, int32_t stage, void* stream)
   const SigArg a = table_arg(b);
   switch (stage) {
     case 0: e = launch_batch_fold(b, b->fold, s); break;
-    case 1: e = launch_bucket_fft(b->dtype, a, b->d_items, b->nitems, b->max_B, s); break;
+    case 1: e = launch_bucket_fft(b->dtype, a, b->d_items, b->d_groups, b->nfft, b->fft_points, s); break;
     case 2: e = launch_recover(b->dtype, a, uint32_t(b->plans.size()), s); break;
     default: return fail(SFFT_ERR_PARAM, "stage must be 0, 1 or 2");
   }

@@ -6,24 +6,44 @@
 
 namespace sfft {
 
+// A workgroup takes a group of rounds with the same B (one round when B is
+// large, up to kFftGroupPoints points of several rounds, of one or several
+// signals, when it is small).  Rounds of different plans may share a group:
+// the twiddles exp(-2 pi i k / B) depend on B only; 1/N is per round.
 template <typename R>
-__global__ __launch_bounds__(256) void bucket_fft_kernel(SigArg arg, const RoundItem* __restrict__ items) {
+__global__ __launch_bounds__(256) void bucket_fft_kernel(SigArg arg, const RoundItem* __restrict__ items,
+                                                         const FftGroup* __restrict__ groups) {
   HIP_DYNAMIC_SHARED(double2, smem_raw)  // 16-byte aligned dynamic LDS
+  constexpr uint32_t kMaxRoundsPerGroup = kFftGroupPoints / 16;  // B >= 16
+  __shared__ cplx<R>* sh_y[kMaxRoundsPerGroup];
+  __shared__ R sh_inv[kMaxRoundsPerGroup];
   cplx<R>* X = reinterpret_cast<cplx<R>*>(smem_raw);
-  const RoundItem itm = items[blockIdx.x];
-  const SignalDesc sd = load_signal(arg, itm.sig);
-  const PlanDesc* pd = sd.plan;
-  const IterDesc* it = pd->iters + itm.m;
-  const uint32_t B = it->B, logB = it->logB;
-  cplx<R>* Y = reinterpret_cast<cplx<R>*>(sd.y) + it->y_off + size_t(itm.j) * B;
-  const cplx<R>* tw = reinterpret_cast<const cplx<R>*>(pd->twiddle) + it->tw_off;
-  for (uint32_t b = threadIdx.x; b < B; b += blockDim.x) X[__brev(b) >> (32 - logB)] = Y[b];
+  const FftGroup grp = groups[blockIdx.x];
+  const RoundItem first = items[grp.first];
+  const SignalDesc sd0 = load_signal(arg, first.sig);
+  const IterDesc* it0 = sd0.plan->iters + first.m;
+  const uint32_t B = it0->B, logB = it0->logB, n = grp.count;
+  const cplx<R>* tw = reinterpret_cast<const cplx<R>*>(sd0.plan->twiddle) + it0->tw_off;
+  for (uint32_t g = threadIdx.x; g < n; g += blockDim.x) {
+    const RoundItem itm = items[grp.first + g];
+    const SignalDesc sd = load_signal(arg, itm.sig);
+    const IterDesc* it = sd.plan->iters + itm.m;
+    sh_y[g] = reinterpret_cast<cplx<R>*>(sd.y) + it->y_off + size_t(itm.j) * B;
+    sh_inv[g] = R(1) / R(sd.plan->N);
+  }
+  __syncthreads();
+  const uint32_t total = n << logB, half_total = total >> 1;
+  for (uint32_t e = threadIdx.x; e < total; e += blockDim.x) {
+    const uint32_t g = e >> logB, b = e & (B - 1);
+    X[(g << logB) + (__brev(b) >> (32 - logB))] = sh_y[g][b];
+  }
   __syncthreads();
   for (uint32_t s = 1; s <= logB; ++s) {
     const uint32_t half = 1u << (s - 1);
-    for (uint32_t k = threadIdx.x; k < B / 2; k += blockDim.x) {
-      const uint32_t pos = k & (half - 1);
-      const uint32_t i0 = ((k >> (s - 1)) << s) + pos, i1 = i0 + half;
+    for (uint32_t k = threadIdx.x; k < half_total; k += blockDim.x) {
+      const uint32_t g = k >> (logB - 1), kk = k & ((B >> 1) - 1);
+      const uint32_t pos = kk & (half - 1);
+      const uint32_t i0 = (g << logB) + ((kk >> (s - 1)) << s) + pos, i1 = i0 + half;
       const cplx<R> w = tw[pos << (logB - s)];
       const cplx<R> a = X[i0], c = cmul(w, X[i1]);
       X[i0] = cadd(a, c);
@@ -31,32 +51,34 @@ __global__ __launch_bounds__(256) void bucket_fft_kernel(SigArg arg, const Round
     }
     __syncthreads();
   }
-  const R inv = R(1) / R(pd->N);
-  for (uint32_t i = threadIdx.x; i < B; i += blockDim.x) Y[i] = cscale(X[i], inv);
+  for (uint32_t e = threadIdx.x; e < total; e += blockDim.x) {
+    const uint32_t g = e >> logB, i = e & (B - 1);
+    sh_y[g][i] = cscale(X[e], sh_inv[g]);
+  }
 }
 
-int launch_bucket_fft(int dtype, const SigArg& sig, const RoundItem* d_items, uint32_t nitems, uint32_t max_B,
-                      void* stream) {
-  if (nitems == 0) return hipSuccess;
+int launch_bucket_fft(int dtype, const SigArg& sig, const RoundItem* d_items, const FftGroup* d_groups,
+                      uint32_t ngroups, uint32_t max_points, void* stream) {
+  if (ngroups == 0) return hipSuccess;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  dim3 grid(nitems), block(256);
+  dim3 grid(ngroups), block(256);
   // up to 128 KiB of dynamic LDS (gfx950 gives a workgroup 160 KiB)
   if (dtype == SFFT_C128) {
-    const size_t lds = size_t(max_B) * 16;
+    const size_t lds = size_t(max_points) * 16;
     if (lds > 65536) {
       const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&bucket_fft_kernel<double>),
                                                hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
       if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(bucket_fft_kernel<double>, grid, block, lds, s, sig, d_items);
+    hipLaunchKernelGGL(bucket_fft_kernel<double>, grid, block, lds, s, sig, d_items, d_groups);
   } else {
-    const size_t lds = size_t(max_B) * 8;
+    const size_t lds = size_t(max_points) * 8;
     if (lds > 65536) {
       const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&bucket_fft_kernel<float>),
                                                hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
       if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(bucket_fft_kernel<float>, grid, block, lds, s, sig, d_items);
+    hipLaunchKernelGGL(bucket_fft_kernel<float>, grid, block, lds, s, sig, d_items, d_groups);
   }
   return hipGetLastError();
 }

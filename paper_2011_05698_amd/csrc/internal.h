@@ -90,6 +90,10 @@ struct RoundItem {                 // one (signal, iteration, round)
   uint32_t sig;
   uint16_t m, j;
 };
+struct FftGroup {                  // round items [first, first + count), all with the same B
+  uint32_t first, count;
+};
+constexpr uint32_t kFftGroupPoints = 2048;  // points one bucket-DFT workgroup takes when B is small
 
 // ------------------------------------------------------------------ host --
 struct IterHost {
@@ -144,8 +148,8 @@ int launch_fold(int dtype, int kahan, const FoldConfig& cfg, const SigArg& sig, 
 // signals, FoldTile.sig = index of the signal group.
 int launch_fold_interleaved(int dtype, int kahan, int unroll, const SignalDesc* table, uint32_t nsig,
                             const FoldTile* d_tiles, uint32_t ntiles, void* stream);
-int launch_bucket_fft(int dtype, const SigArg& sig, const RoundItem* d_items, uint32_t nitems, uint32_t max_B,
-                      void* stream);
+int launch_bucket_fft(int dtype, const SigArg& sig, const RoundItem* d_items, const FftGroup* d_groups,
+                      uint32_t ngroups, uint32_t max_points, void* stream);
 int launch_recover(int dtype, const SigArg& sig, uint32_t nsig, void* stream);
 
 }  // namespace sfft
