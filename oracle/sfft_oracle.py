@@ -30,6 +30,12 @@ in the design notes):
     (Sec. 1, Sec. 3.1: R_m = 2 rounds), is read as offsets tau0 and tau0 + 1
     and the phase-to-position conversion u = round(theta N / 2 pi) mod N
     (Eq. 16 with tau = 1), then the same verification and estimation.
+  * The cross-iteration vote (the one-shot framework that Sec. 1 and the opening
+    of Sec. 3 set against the iterative one: several random bucketizations, a vote over
+    them) is read as: every loop has the full B buckets and w taps, no loop
+    subtracts, a frequency is kept when at least half of the loops located
+    it, and its value is the median over those loops (real and imaginary
+    parts separately).
 """
 
 from __future__ import annotations
@@ -46,7 +52,7 @@ __all__ = [
     "location_schedule", "hash_to_bins", "subtract", "detect", "locate",
     "verify", "estimate", "sfft", "circ_dist", "samples_per_signal",
     "window_spectrum", "bucket_range", "phases", "multiscale_upper_bound",
-    "extension_lower_bound", "BLK", "ENUM", "DIRECT",
+    "extension_lower_bound", "BLK", "ENUM", "DIRECT", "combine_votes",
 ]
 
 TWO_PI = 2.0 * math.pi
@@ -192,25 +198,29 @@ class Plan:
     eta: float
     rho: float
     b_min: int
+    combine: str = "sum"
     iters: list = field(default_factory=list)
 
 
 def make_plan(N, K, B, w, loops, l, q, delta=1e-6, seed=0, b_min=16, eta=1e-4, rho=0.25,
-              location="multiscale") -> Plan:
+              location="multiscale", combine="sum") -> Plan:
     """Per-iteration parameters: B_m = max(B >> (m-1), b_min) buckets (the
     paper halves B per iteration), w_m = floor(w B_m / B) | 1 taps, a fresh
     odd sigma_m and offset tau0_m per iteration from SplitMix64(seed).
     location = "multiscale" (sFFT4.0, Sec. 3.2) or "direct" (the two-round
-    location of sFFT3.0: one step with tau_1 = 1)."""
+    location of sFFT3.0: one step with tau_1 = 1).  combine = "sum" (the
+    iterative framework, Sec. 3.1) or "vote" (the one-shot vote over loops:
+    every loop keeps B_m = B and w_m = w)."""
     assert location in ("multiscale", "direct")
+    assert combine in ("sum", "vote")
     assert N & (N - 1) == 0 and B & (B - 1) == 0
     q = Fraction(q)
     if w % 2 == 0:
         w += 1
     rng = SplitMix64(seed)
-    P = Plan(N, K, B, w, loops, l, q, delta, seed, eta, rho, b_min)
+    P = Plan(N, K, B, w, loops, l, q, delta, seed, eta, rho, b_min, combine)
     for m in range(1, loops + 1):
-        Bm = max(B >> (m - 1), b_min)
+        Bm = B if combine == "vote" else max(B >> (m - 1), b_min)
         Lm = N // Bm
         wm = (w * Bm // B) | 1
         G, info = flat_window(N, Bm, wm, delta)
@@ -380,6 +390,20 @@ def estimate(yhat: np.ndarray, i: int, u: int, it: Iteration, N: int) -> complex
     return complex(np.median(est.real), np.median(est.imag))
 
 
+def combine_votes(votes: dict, loops: int) -> dict:
+    """The vote over loops: votes maps a frequency to the values that the
+    loops which located it estimated.  A frequency is kept when at least
+    half of the loops located it (2 n >= loops); its value is the median of
+    its n values, real and imaginary parts separately (mean of the two
+    middle values for an even n)."""
+    out = {}
+    for f, vs in votes.items():
+        if 2 * len(vs) >= loops:
+            a = np.asarray(vs, dtype=np.complex128)
+            out[f] = complex(np.median(a.real), np.median(a.imag))
+    return out
+
+
 # --------------------------------------------------------------------------
 # The whole method (Sec. 3.1: iterations; output is the K largest, Sec. 2.1).
 # --------------------------------------------------------------------------
@@ -392,10 +416,12 @@ def sfft(x: np.ndarray, P: Plan, trace: bool = False):
     x = np.asarray(x, dtype=np.complex128)
     assert x.shape == (N,)
     rec: dict = {}
+    votes: dict = {}
+    vote = P.combine == "vote"
     info = dict(iters=[])
     for it in P.iters:
         yhat = np.stack([hash_to_bins(x, it.sigma, it.T[j], it.G, it.B) for j in range(it.R + 1)])
-        ysub = subtract(yhat, rec, it, N)
+        ysub = yhat if vote else subtract(yhat, rec, it, N)
         active = detect(ysub, it.B, P.eta, P.rho)
         located = np.full(it.B, -1, dtype=np.int64)
         best: dict = {}
@@ -416,10 +442,15 @@ def sfft(x: np.ndarray, P: Plan, trace: bool = False):
             f = (it.sigma_inv * u) % N
             cands[f] = estimate(ysub, i, u, it, N)
         for f, v in cands.items():
-            rec[f] = rec.get(f, 0j) + v
+            if vote:
+                votes.setdefault(f, []).append(v)
+            else:
+                rec[f] = rec.get(f, 0j) + v
         if trace:
             info["iters"].append(dict(yhat=yhat, ysub=ysub, active=active, located=located,
                                       cands=dict(cands), rec=dict(rec)))
+    if vote:
+        rec = combine_votes(votes, P.loops)
     items = [(f, v) for f, v in rec.items() if v != 0]
     items.sort(key=lambda fv: (-abs(fv[1]), fv[0]))
     items = sorted(items[:P.K])

@@ -341,6 +341,37 @@ def check_p8b_median_rule(O):
         assert abs(got - v) < 1e-9 * abs(v) or (it.R + 1) % 2 == 0
 
 
+def check_p13_vote(O, make_signal):
+    """P13 (the cross-iteration vote over loops, the one-shot framework of
+    Sec. 1 and the opening of Sec. 3).  (a) A vote worked by hand: with 4
+    loops, a frequency located by 3 loops keeps the per-part median of its
+    3 values, one located by 2 loops the mean of the two middle values, one
+    located by 1 loop is dropped.  (b) Every loop of a vote plan has the full
+    B buckets and w taps.  (c) An exactly K-sparse planted signal at
+    K/B = 1/32 comes back (support equal, values within 10 K delta of the
+    truth): with nothing subtracted, a coefficient's estimate in one loop
+    carries the leakage of any other coefficient within reach of its bucket,
+    which at this sparsity happens in few loops, and the median over the
+    loops drops them.  This fails if a loop subtracts what earlier loops
+    found, since later loops then see nothing and the vote drops it.  (d) A single loop is the iterative
+    method's single iteration: same support, same values."""
+    got = O.combine_votes({3: [1 + 1j, 2 + 5j, 3 - 1j], 7: [4j], 9: [1 + 0j, 2 + 2j]}, 4)
+    assert set(got) == {3, 9}, f"P13 vote kept {sorted(got)}"
+    assert got[3] == 2 + 1j and got[9] == 1.5 + 1j, f"P13 vote values {got}"
+    N, K, B, w, M, delta = 2 ** 14, 16, 512, 7169, 8, 1e-8
+    P = O.make_plan(N, K, B, w, M, 16, 1, delta, seed=132, combine="vote")
+    assert all(it.B == B and it.w == w for it in P.iters), "P13 vote plan must keep B and w"
+    x, sup, vals = make_signal(N, K, 131)
+    idx, val, _ = O.sfft(x, P)
+    assert np.array_equal(idx, np.sort(sup)), f"P13 vote support: {len(idx)} of {K}"
+    truth = dict(zip(sup.tolist(), vals))
+    err = max(abs(v - truth[f]) for f, v in zip(idx.tolist(), val))
+    assert err <= 10 * K * delta, f"P13 vote value error {err:.3g}"
+    one_v = O.sfft(x, O.make_plan(N, K, B, w, 1, 16, 1, delta, seed=133, combine="vote"))
+    one_s = O.sfft(x, O.make_plan(N, K, B, w, 1, 16, 1, delta, seed=133))
+    assert np.array_equal(one_v[0], one_s[0]) and np.array_equal(one_v[1], one_s[1]), "P13 single loop"
+
+
 def check_p9_end_to_end(O, cases, make_signal, location="multiscale"):
     """P9: an exactly K-sparse planted signal comes back: the support equals
     the planted support and values are within 10 K delta of the truth;

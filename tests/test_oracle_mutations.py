@@ -55,6 +55,7 @@ CHECKS = {
     "rng": pins.check_splitmix64,
     "p11": pins.check_p11_detect,
     "p12": lambda O: pins.check_p12_direct_location(O, us=range(0, 4096, 5)),
+    "p13": lambda O: pins.check_p13_vote(O, _sig),
 }
 
 MUTANTS = [
@@ -118,6 +119,16 @@ MUTANTS = [
     # direct location: the offset of the second round
     ("lens, taus, kinds = [0, Lm + 2 * e], [0, 1], [BLK, DIRECT]",
      "lens, taus, kinds = [0, Lm + 2 * e], [0, 2], [BLK, DIRECT]", ["p12"]),
+    # vote: a strict majority instead of at least half of the loops
+    ("if 2 * len(vs) >= loops:", "if 2 * len(vs) > loops:", ["p13"]),
+    # vote: mean over the loops instead of the median
+    ("out[f] = complex(np.median(a.real), np.median(a.imag))",
+     "out[f] = complex(np.mean(a.real), np.mean(a.imag))", ["p13"]),
+    # vote: loops also subtract what earlier loops located
+    ("ysub = yhat if vote else subtract(yhat, rec, it, N)",
+     "ysub = subtract(yhat, {f: vs[0] for f, vs in votes.items()} if vote else rec, it, N)", ["p13"]),
+    # vote: B halves per loop as in the iterative method
+    ('Bm = B if combine == "vote" else max(B >> (m - 1), b_min)', "Bm = max(B >> (m - 1), b_min)", ["p13"]),
 ]
 
 

@@ -131,3 +131,7 @@ def test_p12_direct_end_to_end():
     cases = [(2 ** 14, 50, 512, 7169, 8, 16, Fraction(1), 1e-8, 121, 122),
              (2 ** 16, 300, 2048, 32769, 10, 16, Fraction(1), 1e-6, 123, 124)]
     pins.check_p9_end_to_end(O, cases, _signal, location="direct")
+
+
+def test_p13_vote():
+    pins.check_p13_vote(O, _signal)
