@@ -68,13 +68,26 @@ typedef struct sfft_batch_s* sfft_batch_t;
  *       and noise.  Verification and estimation are the same for both. */
 typedef enum { SFFT_LOCATE_MULTISCALE = 0, SFFT_LOCATE_DIRECT = 1 } sfft_location;
 
+/* How the loops' findings are combined:
+ *   SFFT_COMBINE_SUM -- the iterative framework of sFFT4.0 (Sec. 3.1): B_m
+ *       halves per iteration, each iteration first subtracts what earlier ones
+ *       recovered, and rec[f] += v;
+ *   SFFT_COMBINE_VOTE -- the one-shot framework that Sec. 1 and the opening
+ *       of Sec. 3 set against it (several random bucketizations and a vote):
+ *       every loop keeps B and w, no loop subtracts, a frequency is kept when
+ *       at least half of the loops located it (2 n >= loops), and its value is
+ *       the median of its n loop estimates, real and imaginary parts
+ *       separately (mean of the two middle values for an even n).  The
+ *       workspace grows by (sum of B_m) x loops complex values. */
+typedef enum { SFFT_COMBINE_SUM = 0, SFFT_COMBINE_VOTE = 1 } sfft_combine;
+
 typedef struct {
   double delta;     /* window leakage / truncation level, 0 < delta < 0.1 (default 1e-6)   */
   uint64_t seed;    /* SplitMix64 seed of the per-iteration sigma, tau0 draws (default 0)  */
   int32_t dtype;    /* sfft_dtype (default SFFT_C64)                                        */
   int32_t kahan;    /* 1: compensated (Kahan) summation in the fold (default 0)             */
   int32_t b_min;    /* smallest bucket count of late iterations, power of two (default 16) */
-  int32_t pad0;
+  int32_t combine;  /* sfft_combine (default SFFT_COMBINE_SUM)                               */
   double eta;       /* detection floor relative to the strongest bucket (default 1e-4)     */
   double rho;       /* round-to-round magnitude tolerance of a lone bucket (default 0.25)  */
   uint32_t flags;   /* SFFT_PLAN_* bits                                                     */
@@ -92,7 +105,8 @@ void sfft_default_options(sfft_options* opt);
  *   K      number of coefficients returned, 1 <= K <= B.
  *   B      buckets of the first iteration, a power of two, 16 <= B <= N/4
  *          (Sec. 2.3: bucket width L = N/B).  Iteration m uses
- *          B_m = max(B >> (m-1), b_min) buckets (Sec. 3.3: B halves).
+ *          B_m = max(B >> (m-1), b_min) buckets (Sec. 3.3: B halves);
+ *          B_m = B under SFFT_COMBINE_VOTE.
  *   w      window support of the first iteration, B <= w <= N-1; an even w
  *          is rounded up to odd.  Iteration m uses w_m = floor(w B_m / B) | 1.
  *   loops  number of iterations M (Sec. 3.1), 1 <= loops <= 64.

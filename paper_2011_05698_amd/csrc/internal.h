@@ -46,12 +46,13 @@ struct PlanDesc {
   uint32_t fp64_phase;            // take location phases in FP64 (N >= 2^24)
   uint32_t log_hcap;              // hash index of the store: 2^log_hcap >= 2 rec_cap slots
   uint32_t location;              // sfft_location of every iteration
-  uint32_t pad_loc;
+  uint32_t combine;               // sfft_combine
   uint64_t y_total;               // complex elements of bucket values per signal
   uint64_t ws_bytes;              // workspace bytes per signal
   // byte offsets inside one signal's workspace
   uint64_t off_y, off_recf, off_recv, off_htkey, off_htidx, off_candu, off_candd, off_candv;
   uint64_t off_keys, off_p0;
+  uint64_t off_nvote, off_votes;  // vote: loops that located each store entry, and their estimates
   double eta, rho;
   const IterDesc* iters;          // device array of M descriptors
   const void* window;             // float or double table

@@ -151,6 +151,9 @@ sfft_status build_host_plan(HostPlan& hp, int64_t N, int64_t K, int64_t B, int64
   if (opt.location != SFFT_LOCATE_MULTISCALE && opt.location != SFFT_LOCATE_DIRECT)
     return bad(SFFT_ERR_PARAM, "unknown location method");
   const bool direct = opt.location == SFFT_LOCATE_DIRECT;
+  if (opt.combine != SFFT_COMBINE_SUM && opt.combine != SFFT_COMBINE_VOTE)
+    return bad(SFFT_ERR_PARAM, "unknown combine method");
+  const bool vote = opt.combine == SFFT_COMBINE_VOTE;
   const int64_t bmax = opt.dtype == SFFT_C128 ? kMaxBucketsF64 : kMaxBucketsF32;
   if (B > bmax) return bad(SFFT_ERR_UNSUPPORTED, "B above the bucket-FFT limit of this dtype");
 
@@ -179,7 +182,8 @@ sfft_status build_host_plan(HostPlan& hp, int64_t N, int64_t K, int64_t B, int64
   for (int m = 0; m < loops; ++m) {
     IterHost it{};
     IterDesc& d = it.d;
-    int64_t Bm = std::max<int64_t>(B >> m, opt.b_min);
+    // The vote keeps B and w in every loop; the iterative method halves B.
+    int64_t Bm = vote ? B : std::max<int64_t>(B >> m, opt.b_min);
     int64_t Lm = N / Bm;
     int64_t wm = ((w * Bm) / B) | 1;
     d.B = uint32_t(Bm); d.logB = uint32_t(ilog2(Bm)); d.L = uint32_t(Lm); d.logL = uint32_t(ilog2(Lm));
@@ -241,6 +245,7 @@ sfft_status build_host_plan(HostPlan& hp, int64_t N, int64_t K, int64_t B, int64
   PlanDesc& pd = hp.desc;
   std::memset(&pd, 0, sizeof(pd));
   pd.location = opt.location;
+  pd.combine = uint32_t(opt.combine);
   pd.N = uint32_t(N); pd.logN = uint32_t(ilog2(N)); pd.K = uint32_t(K); pd.M = uint32_t(loops);
   pd.l = uint32_t(l); pd.logl = uint32_t(ilog2(l));
   pd.qn = int32_t(qn); pd.logqd = uint32_t(ilog2(qd));
@@ -289,6 +294,9 @@ void layout_workspace(HostPlan& hp) {
   for (auto& it : hp.iters) max_slots = std::max<uint64_t>(max_slots, uint64_t(it.d.reach) + 1);
   pd.off_keys = take(uint64_t(pd.sort_cap) * (4 + 8 + 16 + 8 * max_slots + 16) + uint64_t(pd.Bmax) * 24 + 512);
   pd.off_p0 = take(uint64_t(pd.Bmax) * rs);
+  const bool vote = pd.combine == SFFT_COMBINE_VOTE;
+  pd.off_nvote = take(vote ? uint64_t(pd.rec_cap) * 4 : 0);
+  pd.off_votes = take(vote ? uint64_t(pd.rec_cap) * pd.M * 2 * rs : 0);
   pd.ws_bytes = off;
 }
 

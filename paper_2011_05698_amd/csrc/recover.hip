@@ -4,6 +4,9 @@
 //   singleton detection, multiscale location (Eq. 15-19) and verification,
 //   median estimation (Eq. 14 per round), dedupe, accumulation
 //   rec[f] += v (step 5); finally the K largest coefficients.
+// Under the vote over loops (SFFT_COMBINE_VOTE) no loop subtracts; a store
+// entry keeps one estimate per loop that located it, and the entries that at
+// least half of the loops located take the median of their estimates.
 // One thread per bucket for the per-bucket work.  The recovered store is an
 // append-only array with an open-addressing hash index on the frequency, so an
 // iteration's survivors go straight in; every sum that depends on the store's
@@ -503,6 +506,26 @@ struct TopKey<double> {
   static __device__ __forceinline__ uint32_t freq_of_sorted(T key) { return uint32_t(key.hi); }
 };
 
+// Median of the real (IM = false) or imaginary parts of n loop estimates
+// (mean of the two middle values for an even n), by rank: the value whose
+// rank, ties broken by position, is floor((n-1)/2) and the one of rank
+// floor(n/2).  n <= 64; one thread.
+template <typename R, bool IM>
+__device__ R loop_median(const cplx<R>* vs, uint32_t n) {
+  R lo = R(0), hi = R(0);
+  for (uint32_t a = 0; a < n; ++a) {
+    const R x = IM ? vs[a].im : vs[a].re;
+    uint32_t rank = 0;
+    for (uint32_t b = 0; b < n; ++b) {
+      const R y = IM ? vs[b].im : vs[b].re;
+      rank += (y < x || (y == x && b < a)) ? 1u : 0u;
+    }
+    if (rank == (n - 1) / 2) lo = x;
+    if (rank == n / 2) hi = x;
+  }
+  return (n & 1u) ? lo : (lo + hi) * R(0.5);
+}
+
 template <typename R>
 __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
   __shared__ __attribute__((aligned(16))) unsigned char lds_buf[kLdsBytes];
@@ -535,6 +558,9 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
   R* g_p0 = reinterpret_cast<R*>(ws + pd->off_p0);
   const uint32_t N = pd->N, nmask = N - 1, logN = pd->logN, logh = pd->log_hcap;
   const uint32_t hmask = (1u << logh) - 1;
+  const bool vote = pd->combine == SFFT_COMBINE_VOTE;
+  uint32_t* nvote = reinterpret_cast<uint32_t*>(ws + pd->off_nvote);
+  cplx<R>* votes = reinterpret_cast<cplx<R>*>(ws + pd->off_votes);
 
   // empty store and hash index
   for (uint32_t h = tid; h <= hmask; h += NT) hk[h] = kNone;
@@ -551,6 +577,10 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
     const R* ghat = reinterpret_cast<const R*>(pd->ghat) + it->ghat_off;
     const uint32_t sigma = it->sigma;
 
+    // The vote (SFFT_COMBINE_VOTE) subtracts nothing: every loop sees the
+    // whole signal.
+    const uint32_t nsub = vote ? 0u : nrec;
+
     // ---- LDS plan of the iteration ----
     // The iteration's bucket block ((R+1) x B values) and the per-bucket
     // arrays are staged in LDS when they fit beside the scratch that the
@@ -558,7 +588,7 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
     // workspace.  The subtraction then updates the staged block in place and
     // every later phase reads it from LDS.
     uint32_t npow = 1, logc = 0;
-    while (npow < nrec) {
+    while (npow < nsub) {
       npow <<= 1;
       ++logc;
     }
@@ -568,14 +598,14 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
     // value x phase per entry, one round's sums per bucket
     constexpr uint32_t CB = uint32_t(sizeof(cplx<R>));
     const uint32_t o_sk = (npow * 4u + 15u) & ~15u;
-    const uint32_t o_sv = (o_sk + nrec * 8u + 15u) & ~15u;
-    const uint32_t o_gq = (o_sv + nrec * CB + 15u) & ~15u;
-    const uint32_t o_w = (o_gq + nrec * nslot * uint32_t(sizeof(R)) + 15u) & ~15u;
+    const uint32_t o_sv = (o_sk + nsub * 8u + 15u) & ~15u;
+    const uint32_t o_gq = (o_sv + nsub * CB + 15u) & ~15u;
+    const uint32_t o_w = (o_gq + nsub * nslot * uint32_t(sizeof(R)) + 15u) & ~15u;
     // then per bucket the bounds of its run, and (bucket values in the
     // workspace) the sums of the rounds of one pass; rp rounds share a pass
     auto sub_bytes = [&](uint32_t rp, bool staged) -> uint32_t {
-      if (nrec == 0) return 0u;
-      const uint32_t orun = (o_w + nrec * CB * rp + 15u) & ~15u;
+      if (nsub == 0) return 0u;
+      const uint32_t orun = (o_w + nsub * CB * rp + 15u) & ~15u;
       return orun + B * 8u + (staged ? 0u : B * CB * rp);
     };
     const uint32_t det_need = B * uint32_t(sizeof(typename RK::T));
@@ -591,7 +621,7 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
     const bool pb_lds_plan = fits(1, y_lds, true);
     uint32_t rp = 1;  // more rounds per pass only where the LDS plan above still holds
     while (rp < uint32_t(kMaxRoundsPerPass) && fits(rp * 2, y_lds, pb_lds_plan)) rp *= 2;
-    const uint32_t o_run = (o_w + nrec * CB * rp + 15u) & ~15u;
+    const uint32_t o_run = (o_w + nsub * CB * rp + 15u) & ~15u;
     const uint32_t o_ys = o_run + B * 8u;
     const uint32_t sub_need = sub_bytes(rp, y_lds);
     const uint32_t scr_need = sub_need > det_need ? sub_need : det_need;
@@ -624,7 +654,7 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
     // times that value over the bucket's run, closed by a fixed sequence of
     // cross-lane adds; and the round's sums are taken off the bucket values
     // in one pass.  The order of every sum depends only on the recovered set.
-    if (nrec > 0) {
+    if (nsub > 0) {
       const uint32_t cshift = logN - logc;  // npow <= rec_cap < N
       const bool in_lds = sub_need <= scr_bytes;
       unsigned char* base = in_lds ? scr : reinterpret_cast<unsigned char*>(gkeys);
@@ -638,15 +668,15 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
       cplx<R>* ysub = reinterpret_cast<cplx<R>*>(base + o_ys);
       for (uint32_t c = tid; c < npow; c += NT) cend[c] = 0;
       __syncthreads();
-      for (uint32_t k = tid; k < nrec; k += NT) atomicAdd(&cend[((sigma * rf[k]) & nmask) >> cshift], 1u);
+      for (uint32_t k = tid; k < nsub; k += NT) atomicAdd(&cend[((sigma * rf[k]) & nmask) >> cshift], 1u);
       __syncthreads();
       block_scan_array(cend, npow, wsum);  // cend[c] = start of cell c
-      for (uint32_t k = tid; k < nrec; k += NT) {
+      for (uint32_t k = tid; k < nsub; k += NT) {
         const uint32_t u = (sigma * rf[k]) & nmask;
         tmp[atomicAdd(&cend[u >> cshift], 1u)] = (uint64_t(u) << 32) | k;  // cend[c] ends as the end of cell c
       }
       __syncthreads();
-      for (uint32_t p = tid; p < nrec; p += NT) {  // exact rank inside the cell
+      for (uint32_t p = tid; p < nsub; p += NT) {  // exact rank inside the cell
         const uint64_t key = tmp[p];
         const uint32_t c = uint32_t(key >> 32) >> cshift;
         const uint32_t c0 = c ? cend[c - 1] : 0u, c1 = cend[c];
@@ -657,7 +687,7 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
       __syncthreads();
       // number of sorted entries whose u is below x (x <= N)
       auto lower = [&](uint32_t x) -> uint32_t {
-        if (x >= N) return nrec;
+        if (x >= N) return nsub;
         const uint32_t c = x >> cshift;
         uint32_t q = c ? cend[c - 1] : 0u;
         const uint32_t c1 = cend[c];
@@ -667,23 +697,23 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
       // values in sorted order and the window weight of each bucket an entry
       // reaches (slot r: bucket i0(u) + r, i0 = ceil((u - D) / L)); a thread
       // issues the loads of kVgBatch entries together
-      for (uint32_t qb = 0; qb < nrec; qb += kVgBatch * NT) {
+      for (uint32_t qb = 0; qb < nsub; qb += kVgBatch * NT) {
         uint64_t key[kVgBatch];
         cplx<R> val[kVgBatch];
 #pragma unroll
         for (int e = 0; e < kVgBatch; ++e) {
           const uint32_t q = qb + uint32_t(e) * NT + tid;
-          key[e] = q < nrec ? sk[q] : 0;
+          key[e] = q < nsub ? sk[q] : 0;
         }
 #pragma unroll
         for (int e = 0; e < kVgBatch; ++e) {
           const uint32_t q = qb + uint32_t(e) * NT + tid;
-          val[e] = q < nrec ? rv[uint32_t(key[e])] : cplx<R>{0, 0};
+          val[e] = q < nsub ? rv[uint32_t(key[e])] : cplx<R>{0, 0};
         }
 #pragma unroll
         for (int e = 0; e < kVgBatch; ++e) {
           const uint32_t q = qb + uint32_t(e) * NT + tid;
-          if (q < nrec) {
+          if (q < nsub) {
             const uint32_t u = uint32_t(key[e] >> 32);
             const int64_t i0 = first_bucket(u, D, it->logL);
             sv[q] = val[e];
@@ -702,19 +732,19 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
         const uint32_t a = (i * L - D) & nmask;  // first u of the run
         const uint64_t stop = uint64_t(a) + span;
         const uint32_t q0 = lower(a);
-        const uint32_t cnt = stop <= N ? lower(uint32_t(stop)) - q0 : nrec - q0 + lower(uint32_t(stop - N));
+        const uint32_t cnt = stop <= N ? lower(uint32_t(stop)) - q0 : nsub - q0 + lower(uint32_t(stop - N));
         run[i] = RunBounds{q0, cnt};
       }
       __syncthreads();
       // team size: enough lanes to cover the mean run, as many as let one
       // pass take all buckets (at least 1, at most 64)
-      const double mean_run = double(nrec) * double(2 * D + 1) / double(N);
+      const double mean_run = double(nsub) * double(2 * D + 1) / double(N);
       uint32_t S = 1;
       while (S < 64 && double(S) < mean_run && S * 2u * B <= NT) S <<= 1;
       const uint32_t team = tid / S, lane = tid & (S - 1), nteams = NT / S;
       for (uint32_t j0 = 0; j0 < R1; j0 += rp) {
         const uint32_t nj = min(rp, R1 - j0);
-        for (uint32_t q = tid; q < nrec; q += NT) {
+        for (uint32_t q = tid; q < nsub; q += NT) {
           const uint32_t u = uint32_t(sk[q] >> 32);
           const cplx<R> v = sv[q];
           for (uint32_t r = 0; r < nj; ++r)
@@ -731,7 +761,7 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
             const uint32_t q0 = rb.first, cnt = rb.count;
             for (uint32_t v = lane; v < cnt; v += S) {
               uint32_t q = q0 + v;
-              q = q >= nrec ? q - nrec : q;
+              q = q >= nsub ? q - nsub : q;
               const uint32_t u = uint32_t(sk[q] >> 32);
               const uint32_t slot = (i - uint32_t(first_bucket(u, D, it->logL))) & (B - 1);
               const R g = gq[q * nslot + slot];
@@ -870,7 +900,13 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
         const uint32_t k = hkey(hk, h);
         if (k == f) {  // seen in an earlier iteration
           const uint32_t e = hi[h];
-          rv[e] = cadd(rv[e], v);
+          if (vote) {  // one estimate per loop: at most M per entry
+            const uint32_t c = nvote[e];
+            votes[size_t(e) * pd->M + c] = v;
+            nvote[e] = c + 1;
+          } else {
+            rv[e] = cadd(rv[e], v);
+          }
           break;
         }
         if (k == kNone) {
@@ -879,6 +915,10 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
             const uint32_t e = atomicAdd(&nrec_sh, 1u);
             rf[e] = f;
             rv[e] = v;
+            if (vote) {
+              nvote[e] = 1;
+              votes[size_t(e) * pd->M] = v;
+            }
             hi[h] = e;
             break;
           }
@@ -888,6 +928,16 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
     }
     __syncthreads();
     nrec = nrec_sh;
+    __syncthreads();
+  }
+
+  // ---- the vote over loops: keep f when at least half of the loops located it ----
+  if (vote) {
+    for (uint32_t e = tid; e < nrec; e += NT) {
+      const uint32_t n = nvote[e];
+      const cplx<R>* vs = votes + size_t(e) * pd->M;
+      rv[e] = 2u * n >= pd->M ? cplx<R>{loop_median<R, false>(vs, n), loop_median<R, true>(vs, n)} : cplx<R>{0, 0};
+    }
     __syncthreads();
   }
 

@@ -40,7 +40,7 @@ class SfftError(RuntimeError):
 
 class Options(ctypes.Structure):
     _fields_ = [("delta", ctypes.c_double), ("seed", ctypes.c_uint64), ("dtype", ctypes.c_int32),
-                ("kahan", ctypes.c_int32), ("b_min", ctypes.c_int32), ("pad0", ctypes.c_int32),
+                ("kahan", ctypes.c_int32), ("b_min", ctypes.c_int32), ("combine", ctypes.c_int32),
                 ("eta", ctypes.c_double), ("rho", ctypes.c_double), ("flags", ctypes.c_uint32),
                 ("location", ctypes.c_uint32)]
 
@@ -256,12 +256,14 @@ class Plan:
     """A plan for signals of length N (see sfft_plan in include/sfft.h)."""
 
     def __init__(self, N, K, B, w, loops, multiscale, extension, *, delta=1e-6, seed=0, dtype="c64",
-                 kahan=False, b_min=16, eta=1e-4, rho=0.25, host_only=False, location="multiscale"):
+                 kahan=False, b_min=16, eta=1e-4, rho=0.25, host_only=False, location="multiscale",
+                 combine="sum"):
         o = sfft_default_options()
         o.delta, o.seed, o.dtype, o.kahan, o.b_min = delta, seed, DTYPES[dtype], int(kahan), b_min
         o.eta, o.rho = eta, rho
         o.flags = SFFT_PLAN_HOST_ONLY if host_only else 0
         o.location = {"multiscale": 0, "direct": 1}[location]
+        o.combine = {"sum": 0, "vote": 1}[combine]
         self.dtype = dtype
         self.handle = sfft_plan(N, K, B, w, loops, multiscale, float(Fraction(extension)), o)
         i = sfft_get_plan_info(self.handle)

@@ -45,12 +45,14 @@ PLANS = [
 ]
 
 
+@pytest.mark.parametrize("combine", ["sum", "vote"])
 @pytest.mark.parametrize("location", ["multiscale", "direct"])
 @pytest.mark.parametrize("case", PLANS, ids=lambda c: f"N{c[0]}_B{c[2]}_l{c[5]}_q{c[6]}")
-def test_plan_matches_oracle(case, location):
+def test_plan_matches_oracle(case, location, combine):
     N, K, B, w, M, l, q, delta, seed = case
-    P = O.make_plan(N, K, B, w, M, l, q, delta, seed=seed, location=location)
-    p = sfft.Plan(N, K, B, w, M, l, q, delta=delta, seed=seed, host_only=True, location=location)
+    P = O.make_plan(N, K, B, w, M, l, q, delta, seed=seed, location=location, combine=combine)
+    p = sfft.Plan(N, K, B, w, M, l, q, delta=delta, seed=seed, host_only=True, location=location,
+                  combine=combine)
     assert p.samples == O.samples_per_signal(P)
     off = 0
     for m, it in enumerate(P.iters):
@@ -73,13 +75,15 @@ def test_invalid_parameters_rejected():
     bad = [
         dict(N=1000), dict(N=2 ** 31), dict(B=24), dict(B=2 ** 13), dict(K=0), dict(K=600),
         dict(w=100), dict(w=2 ** 14), dict(loops=0), dict(l=3), dict(l=1), dict(q=0.0), dict(q=0.3),
-        dict(l=2, q=1.0), dict(delta=0.5), dict(delta=0.0),
+        dict(l=2, q=1.0), dict(delta=0.5), dict(delta=0.0), dict(combine=2),
     ]
-    base = dict(N=2 ** 14, K=50, B=512, w=7169, loops=8, l=16, q=1.0, delta=1e-8)
+    base = dict(N=2 ** 14, K=50, B=512, w=7169, loops=8, l=16, q=1.0, delta=1e-8, combine=0)
     for b in bad:
         a = {**base, **b}
+        o = sfft.sfft_default_options()
+        o.delta, o.combine, o.flags = a["delta"], a["combine"], sfft.SFFT_PLAN_HOST_ONLY
         with pytest.raises(sfft.SfftError) as ei:
-            sfft.Plan(a["N"], a["K"], a["B"], a["w"], a["loops"], a["l"], a["q"], delta=a["delta"], host_only=True)
+            sfft.sfft_plan(a["N"], a["K"], a["B"], a["w"], a["loops"], a["l"], a["q"], o)
         assert ei.value.status in (1, 2), b
 
 

@@ -285,6 +285,67 @@ def test_direct_location_denser(sf):
     assert rel_l2(gval, oval) <= 2e-3
 
 
+VOTE = [
+    # N, K, B, w, loops, delta, storage, SNR dB, signal seed, plan seed
+    (2 ** 14, 50, 512, 7169, 8, 1e-8, "c64", None, 101, 102),
+    (2 ** 14, 50, 512, 7169, 8, 1e-8, "c128", None, 101, 102),
+    (2 ** 14, 50, 512, 7169, 5, 1e-8, "c128", 20, 101, 102),
+    (2 ** 16, 200, 2048, 32769, 7, 1e-6, "c64", None, 141, 142),
+]
+
+
+@pytest.mark.parametrize("case", VOTE, ids=lambda c: f"N{c[0]}_K{c[1]}_M{c[4]}_{c[6]}_snr{c[7]}")
+def test_vote_parity(sf, case):
+    """The vote over loops (every loop keeps B and w, nothing is subtracted,
+    a frequency is kept when at least half of the loops located it, value
+    the per-part median of its loop estimates): the GPU path matches the
+    oracle's support bit for bit and its values within 1e-4 (1e-10 in
+    complex128)."""
+    N, K, B, w, M, delta, dt, snr, ss, ps = case
+    x, sup, _ = make_signal(SignalSpec(N, K, ss, snr))
+    xd, scale, xq = to_dev(x, dt)
+    P = O.make_plan(N, K, B, w, M, 16, 1, delta, seed=ps, combine="vote")
+    oidx, oval, _ = O.sfft(xq, P)
+    plan = sf.Plan(N, K, B, w, M, 16, 1.0, delta=delta, seed=ps, dtype=dt, combine="vote")
+    assert all(plan.iteration(m)["B"] == B for m in range(M))
+    gidx, gval, c = run_gpu(sf, plan, xd, scale)
+    assert len(oidx) > 0
+    assert np.array_equal(gidx, oidx)
+    assert rel_l2(gval, oval) <= (1e-10 if dt == "c128" else 1e-4)
+
+
+def test_vote_metric_shape(sf):
+    """The vote at the metric workload's shape (N = 2^22, K = 1000, B = 2048,
+    w = 45057, 12 loops, each with B and w) in the position-major layout: 8
+    signals equal their single executes bit for bit, and two of them match
+    the oracle element by element (support bit for bit, values 1e-4)."""
+    N, K, B, w, M, l, q, delta = 2 ** 22, 1000, 2048, 45057, 12, 16, Fraction(1), 1e-6
+    nsig = 8
+    plan = sf.Plan(N, K, B, w, M, l, q, delta=delta, seed=602, combine="vote")
+    X = torch.zeros((N, nsig), dtype=torch.complex64, device=DEV)
+    xq = {}
+    for s in range(nsig):
+        x, _, _ = make_signal(SignalSpec(N, K, 601 + s))
+        X[:, s] = torch.from_numpy(x.astype(np.complex64)).to(DEV)
+        if s in (0, nsig - 1):
+            xq[s] = x.astype(np.complex64).astype(np.complex128)
+    batch = sf.InterleavedBatch(plan, nsig)
+    idx, val, cnt = batch.execute(X)
+    torch.cuda.synchronize()
+    for s in range(nsig):
+        gi, gv, c = run_gpu(sf, plan, X[:, s].contiguous(), 1.0)
+        assert int(cnt[s].item()) == c
+        assert np.array_equal(idx[s, :c].cpu().numpy(), gi)
+        assert np.array_equal(val[s, :c].cpu().numpy(), gv)
+    P = O.make_plan(N, K, B, w, M, l, q, delta, seed=602, combine="vote")
+    for s, x in xq.items():
+        oidx, oval, _ = O.sfft(x, P)
+        c = int(cnt[s].item())
+        assert c > 0.8 * K
+        assert np.array_equal(idx[s, :c].cpu().numpy(), oidx)
+        assert rel_l2(val[s, :c].cpu().numpy().astype(np.complex128), oval) <= 1e-4
+
+
 def test_batch_uneven_matches_single(sf):
     """Signals of different N and K in one batch give exactly what single
     executes give, and match the oracle."""
