@@ -96,6 +96,109 @@ def measured_traffic(workload_tag):
     return int(float(vals["fold_hbm_bytes_per_launch"])), os.path.relpath(path, ROOT)
 
 
+def experiments(torch, sfft, dev):
+    """The parameter experiments of Sec. 4.2 on the GPU path (none of the
+    comparison systems).  Signals as in Sec. 4.1: K = 50 unit tones, complex
+    white noise at the given SNR.
+
+    fig5: phase error of the two-round phase difference (Eq. 15-17) in
+      buckets that hold one tone, at the four (N, L) of Fig. 5 and SNR from
+      -20 to 120 dB.  The error is the circular distance between
+      arg(yhat_0 conj yhat_1) of the GPU bucket values and the tone's own
+      phase 2 pi (tau_1 u mod N) / N.  Quantiles of log10 of the error.
+    fig6: time per signal vs N (2^14..2^22) for l in {4, 8, 16, 32} at q = 1,
+      and q in {1/4, 1/2, 1, 2, 4} at l = 16, at 20 dB (the general sparse
+      case).  Signals run in position-major batches of 256; plus the fraction
+      of the signal sampled (the method's own curve of Fig. 9).
+    fig7: L1 error vs SNR at N = 2^16 for the same (l, q): the mean over 64
+      signals of (1/K) sum |xhat_f - xhat'_f| over the planted and recovered
+      frequencies (noise not counted).
+    Plans: B = 2^ceil(log2 2K) = 128, w = B log2 N, loops = ceil(log2 K) + 2.
+    l = 2 with q = 1 is not run: the region would not shrink."""
+    import numpy as np
+    from paper_2011_05698_amd.signals import planted_spectrum
+
+    K = 50
+    out = {"fig5": [], "fig6": [], "fig7": []}
+    for N, L in ((8192, 32), (131072, 2048), (1048576, 2048), (4194304, 8192)):
+        B = N // L
+        plan = sfft.Plan(N, K, B, (B * int(math.log2(N))) | 1, 1, 16, 1.0, delta=1e-6, seed=51)
+        it = plan.iteration(0)
+        D, tau1, sig = it["L"] // 2 + it["e"], it["tau"][1], it["sigma"]
+        for snr in (-20, -10, 0, 20, 40, 60, 120):
+            nsig = 24
+            X, _ = make_batch(torch, nsig, N, K, snr, "c64", dev, 5000 + N % 997 + 31 * snr)
+            errs = []
+            for s_ in range(nsig):
+                y = plan.hash_to_bins(X[s_]).cpu().numpy().astype(np.complex128)
+                sup, _ = planted_spectrum(N, K, 5000 + N % 997 + 31 * snr + s_)
+                us = (sig * sup) % N
+                for u in us.tolist():
+                    i = int(round(u / L)) % B
+                    d = np.abs(((us - i * L) + N // 2) % N - N // 2)
+                    if np.count_nonzero(d <= D) != 1:
+                        continue  # another tone reaches this bucket
+                    th = np.angle(y[i] * np.conj(y[B + i]))
+                    ref = 2 * math.pi * ((tau1 * u) % N) / N
+                    errs.append(abs((th - ref + math.pi) % (2 * math.pi) - math.pi))
+            e = np.log10(np.maximum(np.array(errs), 1e-300))
+            out["fig5"].append({"N": N, "L": L, "snr_db": snr, "buckets": len(errs),
+                                "log10_err_p01": round(float(np.quantile(e, 0.01)), 3),
+                                "log10_err_p50": round(float(np.quantile(e, 0.5)), 3),
+                                "log10_err_p99": round(float(np.quantile(e, 0.99)), 3)})
+            log(f"[fig5] N={N} L={L} snr={snr}: {out['fig5'][-1]}")
+    grid = [(l, 1.0) for l in (4, 8, 16, 32)] + [(16, q) for q in (0.25, 0.5, 2.0, 4.0)]
+    B, loops = 128, int(math.ceil(math.log2(K))) + 2
+
+    def l1_error(idx, val, cnt, seeds, N):
+        errs = []
+        for s_, sd in enumerate(seeds):
+            sup, vals = planted_spectrum(N, K, sd)
+            c = int(cnt[s_].item())
+            got = dict(zip(idx[s_, :c].cpu().numpy().tolist(), val[s_, :c].cpu().numpy().astype(np.complex128)))
+            want = dict(zip(sup.tolist(), vals))
+            errs.append(sum(abs(got.get(f, 0) - want.get(f, 0)) for f in set(got) | set(want)) / K)
+        return float(np.mean(errs))
+
+    for logN in (14, 16, 18, 20, 22):
+        N, nsig = 1 << logN, 256
+        X, _ = make_batch(torch, nsig, N, K, 20.0, "c64", dev, 7000 + logN)
+        XT = X.transpose(0, 1).contiguous()
+        del X
+        for l, q in grid:
+            plan = sfft.Plan(N, K, B, (B * logN) | 1, loops, l, q, delta=1e-6, seed=61)
+            b = sfft.InterleavedBatch(plan, nsig)
+            o = b.outputs(dev)
+            for _ in range(2):
+                b.execute(XT, outs=o)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(5):
+                b.execute(XT, outs=o)
+            torch.cuda.synchronize()
+            us = (time.perf_counter() - t0) / (5 * nsig) * 1e6
+            out["fig6"].append({"N": N, "l": l, "q": q, "us_per_signal": round(us, 3),
+                                "sampled_fraction": round(plan.samples / N, 5),
+                                "l1_error_20db": round(l1_error(*o, range(7000 + logN, 7000 + logN + nsig), N), 6)})
+            b.close()
+            log(f"[fig6] {out['fig6'][-1]}")
+        del XT
+    N = 1 << 16
+    for snr in (-10, 0, 10, 20, 30, 40, 60):
+        X, _ = make_batch(torch, 64, N, K, float(snr), "c64", dev, 9000 + snr)
+        XT = X.transpose(0, 1).contiguous()
+        for l, q in grid:
+            plan = sfft.Plan(N, K, B, (B * 16) | 1, loops, l, q, delta=1e-6, seed=71)
+            b = sfft.InterleavedBatch(plan, 64)
+            o = b.execute(XT)
+            torch.cuda.synchronize()
+            out["fig7"].append({"snr_db": snr, "l": l, "q": q,
+                                "l1_error": round(l1_error(*o, range(9000 + snr, 9064 + snr), N), 6)})
+            b.close()
+        log(f"[fig7] snr={snr}: " + ", ".join(f"({r['l']},{r['q']}) {r['l1_error']}" for r in out["fig7"][-len(grid):]))
+    return out
+
+
 def host_copy(torch, X, i, dtype, scale):
     import numpy as np
 
@@ -129,6 +232,8 @@ def main():
                     help="also time the N=2^27, K=8192, B=16384 FP16 workload on this many signals")
     ap.add_argument("--fold-config", default=None, metavar="U,CAP",
                     help="fold launch shape (taps per thread, workgroups per CU cap) instead of tuning")
+    ap.add_argument("--experiments", action="store_true",
+                    help="run the parameter experiments of Sec. 4.2 (Fig. 5-7) instead; prints their JSON")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB a few times (scales HBM byte counters)")
     args = ap.parse_args()
@@ -156,6 +261,9 @@ def main():
     from paper_2011_05698_amd import sfft
 
     dev = torch.device("cuda:0")
+    if args.experiments:
+        print(json.dumps(experiments(torch, sfft, dev)))
+        return
     N, K, B, M, n = args.N, args.K, args.B, args.loops, args.batch
     logN = int(math.log2(N))
     w = (B * logN) | 1
