@@ -75,8 +75,8 @@ def make_batch(torch, n, N, K, snr, dtype, dev, seed0):
 
 def measured_traffic(workload_tag):
     """HBM bytes per fold launch from the committed rocprofv3 summary of this
-    workload and layout, if the fold kernel source is the one the counters
-    were taken with (else None)."""
+    workload and layout, if the fold kernel and its launch order are the ones
+    the counters were taken with (else None)."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", f"fold_kernel_hbm_bytes_{workload_tag}.txt")
@@ -88,9 +88,11 @@ def measured_traffic(workload_tag):
             continue
         k, v = line.split(None, 1)
         vals[k] = v.strip()
-    src = open(os.path.join(ROOT, "paper_2011_05698_amd", "csrc", "fold.hip"), "rb").read()
-    if vals.get("fold_sha256_16") != hashlib.sha256(src).hexdigest()[:16]:
-        return None, "fold kernel changed since the counters were taken"
+    # the kernel (fold.hip) and the order its tiles are launched in (api.hip)
+    csrc = os.path.join(ROOT, "paper_2011_05698_amd", "csrc")
+    src = b"".join(open(os.path.join(csrc, f), "rb").read() for f in ("fold.hip", "api.hip"))
+    if vals.get("fold_sources_sha256_16") != hashlib.sha256(src).hexdigest()[:16]:
+        return None, "fold kernel or its launch order changed since the counters were taken"
     # the launch shape moves no bytes (every shape gathers the same samples), so
     # counters taken at another unroll or cap still price this launch
     return int(float(vals["fold_hbm_bytes_per_launch"])), os.path.relpath(path, ROOT)
