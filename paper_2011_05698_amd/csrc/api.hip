@@ -413,16 +413,12 @@ void interleaved_tiles(const HostPlan& hp, uint32_t ngroups, std::vector<FoldTil
   for (int m = 0; m < hp.loops; ++m) {
     const IterDesc& d = hp.iters[m].d;
     const uint32_t nb = d.B / kIlvItems;  // B >= 16 = kIlvItems
-    for (uint32_t blk = 0; blk < nb; ++blk) {
-      // rounds 0..ujoin in one tile over the union of their windows
-      if (d.ujoin > 0)
-        for (uint32_t g = 0; g < ngroups; ++g) tiles.push_back(FoldTile{g, uint32_t(m), kUnionTile | (blk * kIlvItems)});
-      for (uint32_t j = d.ujoin > 0 ? d.ujoin + 1 : 0; j <= d.R; ++j) {
+    for (uint32_t blk = 0; blk < nb; ++blk)
+      for (uint32_t j = 0; j <= d.R; ++j) {
         const uint32_t shift = ((d.T[j] - d.T[0]) & (d.B - 1)) / kIlvItems;  // B divides N and 2^32
         const uint32_t i0 = j * d.B + ((blk + shift) % nb) * kIlvItems;
         for (uint32_t g = 0; g < ngroups; ++g) tiles.push_back(FoldTile{g, uint32_t(m), i0});
       }
-    }
   }
 }
 

@@ -136,59 +136,6 @@ __global__ __launch_bounds__(256) void fold_interleaved_kernel(const SignalDesc*
   const uint32_t sigma = it->sigma;
   const uint32_t step = (sigma * B) & nmask;
   const R* __restrict__ G = reinterpret_cast<const R*>(pd->window) + it->win_off;
-  if (tl.i0 & kUnionTile) {
-    // Rounds 0..J (J = ujoin, tau_J < w) in one pass over the union of their
-    // windows.  With k = t - tau_j (so x[sigma (k - T_0)] is round j's sample
-    // at tap t), round-0 bucket r and round-j bucket (r + tau_j) mod B gather
-    // the same k = r mod B; each row is loaded once and added to every round
-    // whose window holds it, in ascending t per round, the same sums as one
-    // tile per round.
-    const uint32_t r0 = tl.i0 & ~kUnionTile, J = it->ujoin;
-    const int32_t lo = -h - int32_t(it->tau[J]);
-    const uint32_t T0 = it->T[0];
-    Acc<R, KAHAN> acc[kPerWave][kMaxUnionRounds];
-    for (int q = 0; q < kPerWave; ++q) {
-      const uint32_t r = r0 + wave * kPerWave + q;
-      const int32_t kf = lo + int32_t((r - uint32_t(lo)) & (B - 1));
-      const uint32_t ntaps = uint32_t(h - kf) / B + 1;
-      uint32_t idx = (sigma * (uint32_t(kf) - T0)) & nmask;
-      int32_t k = kf;
-      for (uint32_t k0 = 0; k0 < ntaps; k0 += U) {
-        cplx<R> v[U];
-#pragma unroll
-        for (int e = 0; e < U; ++e) {
-          v[e] = live && k0 + e < ntaps ? Ld::load(xs, uint64_t(idx) * ld) : cplx<R>{0, 0};
-          idx = (idx + step) & nmask;
-        }
-#pragma unroll
-        for (int e = 0; e < U; ++e) {
-          if (k0 + e < ntaps) {
-#pragma unroll
-            for (uint32_t j = 0; j < kMaxUnionRounds; ++j) {
-              const int32_t t = k + e * int32_t(B) + int32_t(it->tau[j]);  // tau[0] = 0
-              if (j <= J && t >= -h && t <= h) acc[q][j].add(G[t < 0 ? -t : t], v[e]);
-            }
-          }
-        }
-        k += U * int32_t(B);
-      }
-    }
-    for (uint32_t j = 0; j <= J; ++j) {
-      for (int q = 0; q < kPerWave; ++q) {
-        cplx<R> out{acc[q][j].re, acc[q][j].im};
-        if (Ld::kScaled) out = cscale(out, scale);
-        tile[wave * kPerWave + q][lane] = out;
-      }
-      __syncthreads();
-      const uint32_t base = j * B, b0 = r0 + it->tau[j];
-      for (uint32_t e = threadIdx.x; e < uint32_t(kIlvItems * kIlvSigs); e += 256) {
-        const uint32_t sl = e / kIlvItems, il = e % kIlvItems;
-        if (s0 + sl < nsig) ys[sl][base + ((b0 + il) & (B - 1))] = tile[il][sl];
-      }
-      __syncthreads();
-    }
-    return;
-  }
   for (int q = 0; q < kPerWave; ++q) {
     const uint32_t item = tl.i0 + wave * kPerWave + q;
     const uint32_t j = item >> logB, b = item & (B - 1);

@@ -22,8 +22,7 @@ struct IterDesc {
   uint32_t R;                     // location steps; the iteration has R + 1 rounds
   uint32_t reach;                 // floor(2D / L): bucket distance of two views of one position
   uint32_t sigma, sigma_inv;      // odd scaling and its inverse mod N
-  uint32_t tau0;
-  uint32_t ujoin;                 // rounds 0..ujoin gather over one union of windows (position-major fold); 0: none
+  uint32_t tau0, pad0;
   uint32_t T[kMaxRounds];         // round offsets: T_0 = tau0, T_j = tau0 + tau_j mod N
   uint32_t tau[kMaxRounds];       // location multipliers (index 0 unused)
   uint32_t len[kMaxRounds];       // location region lengths (index 0 unused)
@@ -143,8 +142,6 @@ struct FoldConfig {
 int fold_lds_bytes(int wg_per_cu);
 constexpr int kIlvItems = 16;      // (round, bucket) items per position-major fold workgroup
 constexpr int kIlvSigs = 64;       // signals per position-major fold workgroup, one per lane
-constexpr uint32_t kUnionTile = 0x80000000u;  // FoldTile.i0 flag: rounds 0..ujoin, round-0 buckets [i0, i0 + kIlvItems)
-constexpr uint32_t kMaxUnionRounds = 4;       // ujoin < kMaxUnionRounds
 int launch_fold(int dtype, int kahan, const FoldConfig& cfg, const SigArg& sig, const FoldTile* d_tiles,
                 uint32_t ntiles, void* stream);
 // Position-major batch (one plan; sample c of signal s at table[s].x + c * ld,

@@ -237,10 +237,6 @@ sfft_status build_host_plan(HostPlan& hp, int64_t N, int64_t K, int64_t B, int64
     d.win_off = win_off;  win_off += d.h + 1;
     d.ghat_off = ghat_off; ghat_off += d.D + 1;
     d.tw_off = tw_off;    tw_off += Bm / 2;
-    // Rounds whose windows overlap round 0's (tau_j < w) can share one gather
-    // of the union of their windows in the position-major fold.
-    d.ujoin = 0;
-    while (d.ujoin < uint32_t(R) && d.ujoin + 1 < kMaxUnionRounds && d.tau[d.ujoin + 1] < uint32_t(wm)) ++d.ujoin;
     d.y_off = y_off;      y_off += uint64_t(R + 1) * uint64_t(Bm);
     hp.samples += int64_t(R + 1) * wm;
     hp.iters.push_back(std::move(it));
