@@ -408,8 +408,22 @@ def test_position_major_matches_single(sf, dtype, kahan, nsig, ld):
     bit for bit what single executes of the same plan give, for a ragged
     last signal group and every storage form; sampled signals match the
     oracle."""
+    _check_position_major(sf, dtype, kahan, nsig, ld)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "f16x2"])
+@pytest.mark.parametrize("location,combine", [("direct", "sum"), ("multiscale", "vote")],
+                         ids=["direct", "vote"])
+def test_position_major_plan_options(sf, dtype, location, combine):
+    """The same for the plan options: the two-round direct location and the
+    vote over loops, in complex64 and FP16 storage."""
+    _check_position_major(sf, dtype, False, 66, 67, location, combine)
+
+
+def _check_position_major(sf, dtype, kahan, nsig, ld, location="multiscale", combine="sum"):
     N, K, B, w, M = 2 ** 14, 40, 512, 7169, 8
-    plan = sf.Plan(N, K, B, w, M, 16, 1.0, delta=1e-6, seed=900, dtype=dtype, kahan=kahan)
+    plan = sf.Plan(N, K, B, w, M, 16, 1.0, delta=1e-6, seed=900, dtype=dtype, kahan=kahan,
+                   location=location, combine=combine)
     xs, scales, xqs, singles = [], [], [], []
     for s in range(nsig):
         # exactly K-sparse, as the method assumes: with fewer tones than K the
@@ -433,7 +447,8 @@ def test_position_major_matches_single(sf, dtype, kahan, nsig, ld):
             assert np.array_equal(idx[s, :c].cpu().numpy(), singles[s][0])
             assert np.array_equal(val[s, :c].cpu().numpy(), singles[s][1])
     for s in (0, nsig - 1):
-        oidx, oval, _ = O.sfft(xqs[s], O.make_plan(N, K, B, w, M, 16, 1, 1e-6, seed=900))
+        oidx, oval, _ = O.sfft(xqs[s], O.make_plan(N, K, B, w, M, 16, 1, 1e-6, seed=900, location=location,
+                                                   combine=combine))
         c = int(cnt[s].item())
         assert np.array_equal(idx[s, :c].cpu().numpy(), oidx)
         tol = 1e-10 if dtype == "c128" else 1e-4
