@@ -900,10 +900,12 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
         const uint32_t k = hkey(hk, h);
         if (k == f) {  // seen in an earlier iteration
           const uint32_t e = hi[h];
-          if (vote) {  // one estimate per loop: at most M per entry
+          if (vote) {  // one estimate per loop (f is unique within a loop): at most M per entry
             const uint32_t c = nvote[e];
-            votes[size_t(e) * pd->M + c] = v;
-            nvote[e] = c + 1;
+            if (c < pd->M) {
+              votes[size_t(e) * pd->M + c] = v;
+              nvote[e] = c + 1;
+            }
           } else {
             rv[e] = cadd(rv[e], v);
           }
