@@ -88,12 +88,26 @@ void group_rounds(std::vector<RoundItem>& items, BOf b_of, std::vector<FftGroup>
 
 // Work lists of one signal, signal-major: the fold covers the (R_m+1) x B_m
 // (round, bucket) items of every iteration in tiles of kFoldTile items.
+// When B_m >= kFoldTile the tiles go out in chunks of 8 bucket blocks: for
+// each round j, the blocks of round j that gather the same positions as the
+// chunk's round-0 blocks (bucket b + (T_j - T_0) mod B), so that tiles 8
+// dispatches apart (the same XCD) share the cache lines they gather.
 void build_work_lists(const HostPlan& hp, uint32_t sig, std::vector<FoldTile>& tiles, std::vector<RoundItem>& items) {
   for (int m = 0; m < hp.loops; ++m) {
     const IterDesc& d = hp.iters[m].d;
     for (uint32_t j = 0; j <= d.R; ++j) items.push_back(RoundItem{sig, uint16_t(m), uint16_t(j)});
-    const uint32_t n = (d.R + 1) * d.B;
-    for (uint32_t i0 = 0; i0 < n; i0 += kFoldTile) tiles.push_back(FoldTile{sig, uint32_t(m), i0});
+    if (d.B < uint32_t(kFoldTile)) {
+      const uint32_t n = (d.R + 1) * d.B;
+      for (uint32_t i0 = 0; i0 < n; i0 += kFoldTile) tiles.push_back(FoldTile{sig, uint32_t(m), i0});
+      continue;
+    }
+    const uint32_t nb = d.B / kFoldTile;  // B and kFoldTile are powers of two
+    for (uint32_t c0 = 0; c0 < nb; c0 += 8)
+      for (uint32_t j = 0; j <= d.R; ++j) {
+        const uint32_t shift = ((d.T[j] - d.T[0]) & (d.B - 1)) / kFoldTile;  // B divides N and 2^32
+        for (uint32_t blk = c0; blk < c0 + 8 && blk < nb; ++blk)
+          tiles.push_back(FoldTile{sig, uint32_t(m), j * d.B + ((blk + shift) % nb) * kFoldTile});
+      }
   }
 }
 
