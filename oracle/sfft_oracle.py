@@ -52,7 +52,7 @@ __all__ = [
     "location_schedule", "hash_to_bins", "subtract", "detect", "locate",
     "verify", "estimate", "sfft", "circ_dist", "samples_per_signal",
     "window_spectrum", "bucket_range", "phases", "multiscale_upper_bound",
-    "extension_lower_bound", "BLK", "ENUM", "DIRECT", "combine_votes",
+    "extension_lower_bound", "BLK", "ENUM", "DIRECT", "combine_votes", "reconstruct",
 ]
 
 TWO_PI = 2.0 * math.pi
@@ -404,6 +404,38 @@ def combine_votes(votes: dict, loops: int) -> dict:
     return out
 
 
+def reconstruct(ysub: np.ndarray, it: Iteration, P: Plan):
+    """One iteration's reconstruction (Sec. 3.2) from its bucket values after
+    subtraction: singleton detection, location and verification of every
+    active bucket, one candidate per located position, and the Eq. 14
+    median estimate of each.  When several buckets locate the same position
+    (a coefficient in the transition band reaches neighbouring buckets), the
+    candidate of the bucket whose centre is nearest is kept, the smaller
+    bucket index on a tie: its window weight Ghat is the largest, so its
+    estimate divides the bucket's error by the most.  Returns
+    (cands {f: v}, active mask, located position per bucket or -1)."""
+    N = P.N
+    active = detect(ysub, it.B, P.eta, P.rho)
+    located = np.full(it.B, -1, dtype=np.int64)
+    best: dict = {}
+    for i in np.flatnonzero(active):
+        i = int(i)
+        th = phases(ysub, i)
+        u = locate(th, i, it, N, P.l, P.q)
+        if not verify(th, u, i, it, N, P.l):
+            continue
+        located[i] = u
+        dist = min(abs(i * it.L - u), N - abs(i * it.L - u))
+        # buckets are visited in ascending order, so a tie keeps the smaller index
+        if u not in best or dist < best[u][0]:
+            best[u] = (dist, i)
+    cands = {}
+    for u, (dist, i) in best.items():
+        f = (it.sigma_inv * u) % N
+        cands[f] = estimate(ysub, i, u, it, N)
+    return cands, active, located
+
+
 # --------------------------------------------------------------------------
 # The whole method (Sec. 3.1: iterations; output is the K largest, Sec. 2.1).
 # --------------------------------------------------------------------------
@@ -422,25 +454,7 @@ def sfft(x: np.ndarray, P: Plan, trace: bool = False):
     for it in P.iters:
         yhat = np.stack([hash_to_bins(x, it.sigma, it.T[j], it.G, it.B) for j in range(it.R + 1)])
         ysub = yhat if vote else subtract(yhat, rec, it, N)
-        active = detect(ysub, it.B, P.eta, P.rho)
-        located = np.full(it.B, -1, dtype=np.int64)
-        best: dict = {}
-        for i in np.flatnonzero(active):
-            i = int(i)
-            th = phases(ysub, i)
-            u = locate(th, i, it, N, P.l, P.q)
-            if not verify(th, u, i, it, N, P.l):
-                continue
-            located[i] = u
-            dist = min(abs(i * it.L - u), N - abs(i * it.L - u))
-            # dedupe: one candidate per position, nearest bucket centre wins,
-            # the smaller bucket index on a tie (i ascends here).
-            if u not in best or dist < best[u][0]:
-                best[u] = (dist, i)
-        cands = {}
-        for u, (dist, i) in best.items():
-            f = (it.sigma_inv * u) % N
-            cands[f] = estimate(ysub, i, u, it, N)
+        cands, active, located = reconstruct(ysub, it, P)
         for f, v in cands.items():
             if vote:
                 votes.setdefault(f, []).append(v)

@@ -471,3 +471,135 @@ def check_p11_detect(O, N=4096, B=64, delta=1e-8, seed=21):
     assert act.sum() == 1, "P11 empty bucket detected"
     assert np.array_equal(O.detect(yh * 1e-3, B, P.eta, P.rho), act)
     assert not O.detect(np.zeros_like(yh), B, P.eta, P.rho).any()
+
+
+def _exact_phases(it, u, v, N, i):
+    """Round phases of bucket i for a lone noiseless coefficient at u, taken
+    from its exact Lemma 1 bucket values (P3's closed form)."""
+    yh = np.zeros((it.R + 1, it.B), dtype=complex)
+    yh[:, i] = _single_tone_yhat(it, u, v, N, i)
+    return [0.0] + [math.atan2((yh[0, i] * np.conj(yh[j, i])).imag, (yh[0, i] * np.conj(yh[j, i])).real)
+                    % TWO_PI for j in range(1, it.R + 1)]
+
+
+def check_p14_verify(O, N=4096, B=64, lq=((16, Fraction(1)), (4, Fraction(1, 4))), delta=1e-8, seed=17):
+    """P14 (Eq. 18 bound, Sec. 3.2): a location is trusted only while every
+    round's phase error is at most half a block, pi/l, and the position lies
+    where the bucket's window reaches (|iL - u| <= L/2 + e).  For lone
+    coefficients at many positions and from every bucket that reaches them,
+    verify accepts the exact phases; it accepts a phase error of
+    (1 - 1e-9) pi/l in any one round, of either sign, and rejects
+    (1 + 1e-9) pi/l in any one round.  A position one step beyond the reach
+    is rejected even with exact phases; one exactly at the reach is kept."""
+    w = (B * int(math.log2(N))) | 1
+    r = rng(seed)
+    v = complex(0.6, 0.8)
+    for l, q in lq:
+        it = O.make_plan(N, 1, B, w, 1, l, q, delta, seed=seed).iters[0]
+        tol = math.pi / l
+        for u in r.choice(N, size=40, replace=False).tolist():
+            for i_unwrapped in O.bucket_range(u, it.L, it.D):
+                i = i_unwrapped % B
+                th = _exact_phases(it, u, v, N, i)
+                assert O.verify(th, u, i, it, N, l), f"P14 exact phases rejected (u={u}, i={i})"
+                for j in range(1, it.R + 1):
+                    for sgn in (1.0, -1.0):
+                        inside = list(th)
+                        inside[j] = (th[j] + sgn * tol * (1 - 1e-9)) % TWO_PI
+                        assert O.verify(inside, u, i, it, N, l), f"P14 error inside pi/l rejected (l={l}, j={j})"
+                        outside = list(th)
+                        outside[j] = (th[j] + sgn * tol * (1 + 1e-9)) % TWO_PI
+                        assert not O.verify(outside, u, i, it, N, l), \
+                            f"P14 error beyond pi/l accepted (l={l}, j={j}, sign {sgn})"
+        # the reach: exact phases of a position at distance D and D + 1
+        for i in (0, 5, B - 1):
+            for side in (1, -1):
+                u_in = (i * it.L + side * it.D) % N
+                u_out = (i * it.L + side * (it.D + 1)) % N
+                assert O.verify(_exact_phases(it, u_in, v, N, i), u_in, i, it, N, l), "P14 reach edge rejected"
+                th = [0.0] + [TWO_PI * ((it.taus[j] * u_out) % N) / N for j in range(1, it.R + 1)]
+                assert not O.verify(th, u_out, i, it, N, l), "P14 position beyond the reach accepted"
+
+
+def check_p15_dedupe(O, N=4096, B=64, delta=1e-8, seed=19):
+    """P15 (dedupe of one position seen by two buckets; Eq. 14 error
+    propagation): a lone coefficient v at u between the centres of buckets
+    i (distance 10) and i + 1 (distance L - 10), both within the window's
+    reach, is located from both.  Each bucket carries an error c, placed in
+    every round so that it shifts every round's Eq. 14 estimate by the same
+    amount c / Ghat: the estimate of bucket k is then exactly
+    v + c / Ghat_{d_k}.  The candidate kept must be the nearer bucket's,
+    within |c| / Ghat_10 (1e-12 relative), not the farther one's, which is
+    off by |c| / Ghat_{L-10} (orders of magnitude more)."""
+    w = (B * int(math.log2(N))) | 1
+    P = O.make_plan(N, 1, B, w, 1, 16, 1, delta, seed=seed)
+    it = P.iters[0]
+    L = it.L
+    v = complex(-0.8, 0.6)
+    c = complex(3e-7, -4e-7)
+    for i, offset in ((7, 10), (30, L - 10), (B - 1, 10)):
+        u = (i * L + offset) % N
+        near = i if offset < L // 2 else (i + 1) % B
+        far = (i + 1) % B if offset < L // 2 else i
+        d_near, d_far = min(offset, L - offset), L - min(offset, L - offset)
+        assert d_far <= it.D, "the farther bucket must reach the coefficient"
+        g_near, g_far = it.Ghat[d_near], it.Ghat[d_far]
+        assert g_far < 0.05 * g_near and g_far > 10 * P.eta
+        yh = np.zeros((it.R + 1, B), dtype=complex)
+        for k in (near, far):
+            yh[:, k] = _single_tone_yhat(it, u, v, N, k)
+            # an error that Eq. 14 turns into the same shift c / Ghat in every round
+            yh[:, k] += np.array([c * np.exp(-2j * np.pi * ((it.T[j] * u) % N) / N) for j in range(it.R + 1)])
+        cands, active, located = O.reconstruct(yh, it, P)
+        assert active[near] and active[far], "P15 both buckets must pass detection"
+        assert located[near] == u and located[far] == u, "P15 both buckets must locate u"
+        f = (it.sigma_inv * u) % N
+        assert list(cands) == [f], f"P15 one candidate per position, got {sorted(cands)}"
+        want = v + c / g_near
+        assert abs(cands[f] - want) <= 1e-12 * abs(v), \
+            f"P15 kept the farther bucket's estimate ({abs(cands[f] - v):.3g} from v)"
+
+
+def check_p16_eta_floor(O, N=4096, B=64, delta=1e-8, seed=23):
+    """P16 (the relative detection floor eta of the detection reading): in
+    one iteration, a strong lone coefficient (1.0), a weaker one (3e-3) and
+    a weak one (3e-5, below eta = 1e-4 of the strongest) sit in separate
+    buckets above a noise floor of 1e-9 in every bucket.  The weak bucket
+    clears the noise threshold 2 ln(B) median|yhat_0|^2 / ln 2 by far, but
+    not the floor (eta max|yhat_0|)^2: the two others are detected, it is
+    not.  With eta = 0 it is detected too.  Scaling all values keeps the
+    decisions."""
+    w = (B * int(math.log2(N))) | 1
+    P = O.make_plan(N, 2, B, w, 1, 4, Fraction(1, 4), delta, seed=seed)
+    it = P.iters[0]
+    L = it.L
+    r = rng(seed)
+    yh = 1e-9 * (r.standard_normal((it.R + 1, B)) + 1j * r.standard_normal((it.R + 1, B)))
+    yh[:, 10] += _single_tone_yhat(it, 10 * L, 1.0 + 0j, N, 10)
+    yh[:, 40] += _single_tone_yhat(it, 40 * L + 1, complex(0, 3e-5), N, 40)
+    # 3e-3 of the strongest: above the floor (a power ratio of eta^2 = 1e-8)
+    yh[:, 25] += _single_tone_yhat(it, 25 * L - 2, complex(-3e-3, 0), N, 25)
+    p0 = np.abs(yh[0]) ** 2
+    assert p0[40] > 1e3 * 2 * math.log(B) * np.median(p0) / math.log(2), "weak bucket must clear the noise threshold"
+    act = O.detect(yh, B, P.eta, P.rho)
+    assert act[10] and act[25] and not act[40], f"P16 eta floor: active buckets {np.flatnonzero(act).tolist()}"
+    assert act.sum() == 2
+    assert np.array_equal(O.detect(yh * 1e4, B, P.eta, P.rho), act)
+    no_floor = O.detect(yh, B, 0.0, P.rho)
+    assert no_floor[10] and no_floor[25] and no_floor[40], "P16 without the floor all three are lone coefficients"
+    # The noise threshold: buckets of pure noise whose magnitude is the same
+    # in every round (so the round-to-round test cannot reject them) and
+    # whose power is exponentially distributed with mean mu.  The median
+    # power is mu ln 2, so nu = mu and the threshold 2 ln(B) mu is exceeded
+    # with probability exp(-2 ln B) = 1/B^2 per bucket: across B buckets a
+    # noise bucket passes with probability 1/B.  All of them sit far above
+    # the eta floor of the strongest bucket, a lone coefficient of 1.0.
+    for B2 in (64, 256):
+        it2 = O.make_plan(N, 2, B2, (B2 * int(math.log2(N))) | 1, 1, 4, Fraction(1, 4), delta, seed=seed).iters[0]
+        mag = np.sqrt(r.exponential(2e-6, size=B2))
+        ph = r.uniform(0, TWO_PI, size=(it2.R + 1, B2))
+        yn = mag[None, :] * np.exp(1j * ph)
+        yn[:, 3] = _single_tone_yhat(it2, 3 * it2.L, 1.0 + 0j, N, 3)
+        act = O.detect(yn, B2, P.eta, P.rho)
+        assert act[3] and act.sum() == 1, f"P16 noise buckets detected: {np.flatnonzero(act).tolist()}"
+        assert O.detect(yn, B2, 0.0, P.rho).sum() == 1

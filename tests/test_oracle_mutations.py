@@ -56,6 +56,9 @@ CHECKS = {
     "p11": pins.check_p11_detect,
     "p12": lambda O: pins.check_p12_direct_location(O, us=range(0, 4096, 5)),
     "p13": lambda O: pins.check_p13_vote(O, _sig),
+    "p14": pins.check_p14_verify,
+    "p15": pins.check_p15_dedupe,
+    "p16": pins.check_p16_eta_floor,
 }
 
 MUTANTS = [
@@ -129,6 +132,31 @@ MUTANTS = [
      "ysub = subtract(yhat, {f: vs[0] for f, vs in votes.items()} if vote else rec, it, N)", ["p13"]),
     # vote: B halves per loop as in the iterative method
     ('Bm = B if combine == "vote" else max(B >> (m - 1), b_min)', "Bm = max(B >> (m - 1), b_min)", ["p13"]),
+    # verify: the per-round phase test (Eq. 18 bound) dropped
+    ("        if circ_dist(theta[j], TWO_PI * ((it.taus[j] * u) % N) / N) > math.pi / l:\n            return False\n",
+     "        pass\n", ["p14", "p7"]),
+    # verify: tolerance of a whole block (2 pi / l) instead of half a block
+    ("((it.taus[j] * u) % N) / N) > math.pi / l:", "((it.taus[j] * u) % N) / N) > 2 * math.pi / l:", ["p14"]),
+    # verify: tolerance a quarter block
+    ("((it.taus[j] * u) % N) / N) > math.pi / l:", "((it.taus[j] * u) % N) / N) > 0.5 * math.pi / l:", ["p14"]),
+    # verify: the reach check dropped
+    ("    if dist > it.D:\n        return False\n    for j", "    for j", ["p14"]),
+    # verify: the reach one position short
+    ("    if dist > it.D:\n        return False\n    for j", "    if dist >= it.D:\n        return False\n    for j", ["p14"]),
+    # dedupe: the farther bucket centre wins
+    ("if u not in best or dist < best[u][0]:", "if u not in best or dist > best[u][0]:", ["p15"]),
+    # dedupe: the last bucket that located the position wins
+    ("if u not in best or dist < best[u][0]:", "if True:", ["p15"]),
+    # detection: the relative floor eta dropped
+    ("thr = max(2.0 * math.log(B) * nu, eta * eta * float(p0.max()))", "thr = 2.0 * math.log(B) * nu", ["p16"]),
+    # detection: the noise threshold dropped (only the relative floor left)
+    ("thr = max(2.0 * math.log(B) * nu, eta * eta * float(p0.max()))", "thr = eta * eta * float(p0.max())", ["p16"]),
+    # detection: the noise threshold without the union bound over B buckets
+    ("thr = max(2.0 * math.log(B) * nu, eta * eta * float(p0.max()))",
+     "thr = max(2.0 * nu, eta * eta * float(p0.max()))", ["p16"]),
+    # detection: the floor applied to magnitudes instead of powers
+    ("thr = max(2.0 * math.log(B) * nu, eta * eta * float(p0.max()))",
+     "thr = max(2.0 * math.log(B) * nu, eta * float(p0.max()))", ["p16", "p9"]),
 ]
 
 
@@ -146,5 +174,5 @@ def test_planted_mistake_is_caught(old, new, checks):
 
 def test_unmutated_oracle_passes_the_same_checks():
     O = importlib.import_module("oracle.sfft_oracle")
-    for name in ("p1", "p2", "p5", "p6", "p8", "sched", "rng"):
+    for name in ("p1", "p2", "p5", "p6", "p8", "sched", "rng", "p14", "p15", "p16"):
         CHECKS[name](O)

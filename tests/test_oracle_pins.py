@@ -135,3 +135,15 @@ def test_p12_direct_end_to_end():
 
 def test_p13_vote():
     pins.check_p13_vote(O, _signal)
+
+
+def test_p14_verify_bound_and_reach():
+    pins.check_p14_verify(O)
+
+
+def test_p15_dedupe_nearest_bucket():
+    pins.check_p15_dedupe(O)
+
+
+def test_p16_detection_floor():
+    pins.check_p16_eta_floor(O)
