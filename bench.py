@@ -201,6 +201,41 @@ def experiments(torch, sfft, dev):
     return out
 
 
+def host_cpu():
+    """CPU model and logical CPU count of this host (lscpu fields)."""
+    info = {"logical_cpus": os.cpu_count()}
+    try:
+        import subprocess
+
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for ln in out.splitlines():
+            k, _, v = ln.partition(":")
+            if k.strip() in ("Model name", "CPU(s)", "Thread(s) per core", "Core(s) per socket", "Socket(s)"):
+                info[k.strip()] = v.strip()
+    except Exception as exc:  # lscpu missing: keep the count alone
+        info["lscpu"] = f"unavailable ({exc.__class__.__name__})"
+    return info
+
+
+class one_thread:
+    """Limits the BLAS and OpenMP thread pools of this process to one thread
+    while the oracle is timed; yields the pools seen (library, threads)."""
+
+    def __enter__(self):
+        try:
+            from threadpoolctl import threadpool_info, threadpool_limits
+        except ImportError:
+            self.ctl = None
+            return [{"threadpoolctl": "unavailable"}]
+        self.ctl = threadpool_limits(limits=1)
+        return [{"library": p.get("internal_api"), "threads": p.get("num_threads")} for p in threadpool_info()]
+
+    def __exit__(self, *exc):
+        if self.ctl is not None:
+            self.ctl.restore_original_limits()
+        return False
+
+
 def host_copy(torch, X, i, dtype, scale):
     import numpy as np
 
@@ -625,11 +660,13 @@ def main():
         idxs, vals, counts = outs
         cnt = counts.cpu().numpy()
         spent, done, same, worst = 0.0, 0, 0, 0.0
+        host = host_cpu()
         while done < n and (spent < args.cpu_seconds or done == 0):
             xh = host_copy(torch, X, done, dt, scales[done])
-            t1 = time.perf_counter()
-            oi, ov, _ = O.sfft(xh, P)
-            spent += time.perf_counter() - t1
+            with one_thread() as pools:
+                t1 = time.perf_counter()
+                oi, ov, _ = O.sfft(xh, P)
+                spent += time.perf_counter() - t1
             c = int(cnt[done])
             gi = idxs[done][:c].cpu().numpy()
             gv = vals[done][:c].cpu().numpy().astype(np.complex128)
@@ -638,7 +675,10 @@ def main():
                 worst = max(worst, float(np.linalg.norm(gv - ov) / max(np.linalg.norm(ov), 1e-300)))
             done += 1
         cpu = {"value": round(done / spent, 4), "unit": "signals/s", "cores": 1, "kind": "oracle",
-               "sample": f"first {done} signals of the batch (same inputs), FP64 NumPy oracle, plan untimed"}
+               "sample": f"first {done} signals of the batch (same inputs), FP64 NumPy oracle, plan untimed",
+               "threads": "one: BLAS/OpenMP pools limited to 1 thread while timed (threadpoolctl); "
+                          "NumPy's FFT, sort and bincount are single-threaded",
+               "thread_pools_during_timing": pools, "host_cpu": host}
         parity = {"signals_checked": done, "support_identical": same, "max_rel_l2_identical": worst}
         log(f"oracle: {done} signals in {spent:.1f}s; parity {same}/{done}, max rel-L2 {worst:.2e}")
         # the other forms, a few signals each (not timed)

@@ -22,6 +22,11 @@
  *     anything is enqueued.  Kernel launch failures return SFFT_ERR_LAUNCH.
  *     sfft_last_error() returns a thread-local description of the most
  *     recent failure on the calling thread.
+ *   - SFFT_ERR_ALLOC: sfft_plan and the batch constructors release whatever
+ *     they had allocated and leave *out NULL.  For tests of this path, the
+ *     environment variable SFFT_FAIL_ALLOC=n makes the n-th host or device
+ *     allocation of such a call (counted from the call's start, on the
+ *     calling thread) fail as if memory were exhausted.
  *   - Complex values are interleaved (re, im): float2 for SFFT_C64 and
  *     SFFT_F16X2_SCALED outputs, double2 for SFFT_C128.
  */
@@ -274,9 +279,11 @@ typedef struct {
 } sfft_fold_config;
 
 /* SFFT_ERR_PARAM for a shape outside the list above (fold_ms is ignored).
- * The batch form waits for the device when the batch already holds a
- * captured graph, drops it, and captures again on the next
- * sfft_execute_batch; bound buffers stay bound. */
+ * The batch form, when the batch already holds a captured graph, waits for
+ * that batch's last replay to finish (an event recorded after it on the
+ * caller's stream; other work on the device is not waited for), drops the
+ * graph, and captures again on the next sfft_execute_batch; bound buffers
+ * stay bound. */
 sfft_status sfft_plan_set_fold_config(sfft_plan_t p, const sfft_fold_config* cfg);
 sfft_status sfft_batch_set_fold_config(sfft_batch_t b, const sfft_fold_config* cfg);
 

@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -16,6 +17,26 @@ namespace sfft {
 
 static thread_local std::string g_last_error;
 void set_last_error(const std::string& s) { g_last_error = s; }
+
+static thread_local long t_alloc_count = 0;
+void alloc_trial_begin() { t_alloc_count = 0; }
+bool alloc_should_fail() {
+  const long k = ++t_alloc_count;
+  const char* s = std::getenv("SFFT_FAIL_ALLOC");
+  if (!s || !*s) return false;
+  char* end = nullptr;
+  const long n = std::strtol(s, &end, 10);
+  return end != s && n > 0 && n == k;
+}
+
+// Device allocation through the failure-injection point.
+static hipError_t dev_malloc(void** p, size_t bytes) {
+  if (alloc_should_fail()) {
+    *p = nullptr;
+    return hipErrorOutOfMemory;
+  }
+  return hipMalloc(p, bytes);
+}
 
 }  // namespace sfft
 
@@ -48,6 +69,8 @@ struct sfft_batch_s {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipStream_t capture_stream = nullptr;
+  hipEvent_t replayed = nullptr;    // recorded on the caller's stream after each graph replay
+  bool replay_recorded = false;
   FoldConfig fold{8, 0};
   bool interleaved = false;         // one plan, position-major signals (sfft_batch_create_interleaved)
   uint32_t ngroups = 0;             // interleaved: signal groups of kIlvSigs
@@ -152,7 +175,7 @@ sfft_status upload_plan(sfft_plan_t p) {
   const uint64_t o_groups = take(sizeof(FftGroup) * groups.size());
   const uint64_t o_ws = take(hp.desc.ws_bytes);
 
-  hipError_t e = hipMalloc(&p->d_mem, off);
+  hipError_t e = dev_malloc(reinterpret_cast<void**>(&p->d_mem), off);
   if (e != hipSuccess) {
     p->d_mem = nullptr;
     return hip_fail(e, "hipMalloc(plan)");
@@ -302,7 +325,8 @@ sfft_status sfft_plan(sfft_plan_t* out, int64_t N, int64_t K, int64_t B, int64_t
   sfft_options o;
   sfft_default_options(&o);
   if (opt) o = *opt;
-  sfft_plan_t p = new (std::nothrow) sfft_plan_s();
+  alloc_trial_begin();
+  sfft_plan_t p = alloc_should_fail() ? nullptr : new (std::nothrow) sfft_plan_s();
   if (!p) return fail(SFFT_ERR_ALLOC, "host allocation of the plan failed");
   std::string err;
   sfft_status st;
@@ -436,7 +460,7 @@ void interleaved_tiles(const HostPlan& hp, uint32_t ngroups, std::vector<FoldTil
   }
 }
 
-sfft_status create_batch(sfft_batch_t* out, const sfft_plan_t* h_plans, int32_t n, bool interleaved) {
+sfft_status create_batch_impl(sfft_batch_t* out, const sfft_plan_t* h_plans, int32_t n, bool interleaved) {
   if (!out || !h_plans || n < 1) return fail(SFFT_ERR_PARAM, "need at least one plan");
   *out = nullptr;
   for (int32_t s = 0; s < n; ++s) {
@@ -445,8 +469,12 @@ sfft_status create_batch(sfft_batch_t* out, const sfft_plan_t* h_plans, int32_t 
     if (h_plans[s]->hp.dtype != h_plans[0]->hp.dtype || h_plans[s]->hp.kahan != h_plans[0]->hp.kahan)
       return fail(SFFT_ERR_PARAM, "all plans of a batch must share dtype and kahan");
   }
-  sfft_batch_t b = new (std::nothrow) sfft_batch_s();
+  sfft_batch_t b = alloc_should_fail() ? nullptr : new (std::nothrow) sfft_batch_s();
   if (!b) return fail(SFFT_ERR_ALLOC, "host allocation of the batch failed");
+  struct Guard {  // releases the half-built batch if a host container throws
+    sfft_batch_t b;
+    ~Guard() { delete b; }
+  } guard{b};
   b->plans.assign(h_plans, h_plans + n);
   b->dtype = h_plans[0]->hp.dtype;
   b->kahan = h_plans[0]->hp.kahan;
@@ -477,11 +505,8 @@ sfft_status create_batch(sfft_batch_t* out, const sfft_plan_t* h_plans, int32_t 
   const uint64_t o_items = o_tiles + align256(sizeof(FoldTile) * tiles.size());
   const uint64_t o_groups = o_items + align256(sizeof(RoundItem) * items.size());
   const uint64_t o_ws = o_groups + align256(sizeof(FftGroup) * groups.size());
-  hipError_t e = hipMalloc(&b->d_mem, o_ws + ws);
-  if (e != hipSuccess) {
-    delete b;
-    return hip_fail(e, "hipMalloc(batch)");
-  }
+  hipError_t e = dev_malloc(reinterpret_cast<void**>(&b->d_mem), o_ws + ws);
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc(batch)");
   b->d_sigs = reinterpret_cast<SignalDesc*>(b->d_mem + o_sigs);
   b->d_tiles = reinterpret_cast<FoldTile*>(b->d_mem + o_tiles);
   b->d_items = reinterpret_cast<RoundItem*>(b->d_mem + o_items);
@@ -491,13 +516,26 @@ sfft_status create_batch(sfft_batch_t* out, const sfft_plan_t* h_plans, int32_t 
   if (e == hipSuccess) e = hipMemcpy(b->d_items, items.data(), sizeof(RoundItem) * items.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(b->d_groups, groups.data(), sizeof(FftGroup) * groups.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->replayed, hipEventDisableTiming);
   if (e != hipSuccess) {
+    if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
     (void)hipFree(b->d_mem);
-    delete b;
     return hip_fail(e, "batch setup");
   }
+  guard.b = nullptr;
   *out = b;
   return SFFT_OK;
+}
+
+// Host containers of the work lists may throw on exhaustion; nothing throws
+// across the ABI.
+sfft_status create_batch(sfft_batch_t* out, const sfft_plan_t* h_plans, int32_t n, bool interleaved) {
+  alloc_trial_begin();
+  try {
+    return create_batch_impl(out, h_plans, n, interleaved);
+  } catch (const std::bad_alloc&) {
+    return fail(SFFT_ERR_ALLOC, "host allocation failed while building the batch");
+  }
 }
 
 sfft_status sfft_batch_create(sfft_batch_t* out, const sfft_plan_t* h_plans, int32_t n) {
@@ -537,7 +575,9 @@ sfft_status bind_and_replay(sfft_batch_t b, const std::vector<SignalDesc>& sig, 
     }
   }
   hipError_t e = hipGraphLaunch(b->exec, s);
+  if (e == hipSuccess) e = hipEventRecord(b->replayed, s);
   if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  b->replay_recorded = true;
   return SFFT_OK;
 }
 
@@ -622,14 +662,15 @@ sfft_status sfft_batch_set_fold_config(sfft_batch_t b, const sfft_fold_config* c
   if (!b || !valid_fold(cfg)) return fail(SFFT_ERR_PARAM, "invalid fold configuration");
   b->fold = FoldConfig{cfg->unroll, cfg->wg_per_cu};
   if (b->exec || b->graph) {
-    // the captured graph holds the old kernel choice: let any replay in
-    // flight end, drop the graph, and capture again on the next execute
-    const hipError_t e = hipDeviceSynchronize();
+    // the captured graph holds the old kernel choice: let this batch's last
+    // replay end (its event on the caller's stream), drop the graph, and
+    // capture again on the next execute
+    const hipError_t e = b->replay_recorded ? hipEventSynchronize(b->replayed) : hipSuccess;
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     b->exec = nullptr;
     b->graph = nullptr;
-    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
   }
   return SFFT_OK;
 }
@@ -681,6 +722,8 @@ sfft_status sfft_batch_autotune(sfft_batch_t b, void* stream, sfft_fold_config* 
 
 sfft_status sfft_batch_destroy(sfft_batch_t b) {
   if (!b) return SFFT_OK;
+  if (b->replay_recorded) (void)hipEventSynchronize(b->replayed);  // the last replay reads this memory
+  if (b->replayed) (void)hipEventDestroy(b->replayed);
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);

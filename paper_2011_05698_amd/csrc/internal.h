@@ -127,6 +127,16 @@ void layout_workspace(HostPlan& hp);
 
 void set_last_error(const std::string& s);
 
+// Allocation-failure injection, for tests of the error paths.  Every host or
+// device allocation the library makes while building a plan or a batch first
+// asks alloc_should_fail(); when the environment variable SFFT_FAIL_ALLOC
+// holds a positive integer n, the n-th such allocation of a public call
+// (counted from the call's start, on the calling thread) fails as if memory
+// were exhausted, and the call returns SFFT_ERR_ALLOC after releasing
+// everything it had taken.  Unset or 0: never.
+void alloc_trial_begin();
+bool alloc_should_fail();
+
 // Stage launchers (kernels.hip).  Each returns hipSuccess or the launch error.
 // All signals of one launch share dtype and the Kahan setting.
 constexpr int kFoldTile = 256;      // (round, bucket) items per fold work item (one thread each)

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <new>
 #include <thread>
 
 #include "internal.h"
@@ -180,6 +181,7 @@ sfft_status build_host_plan(HostPlan& hp, int64_t N, int64_t K, int64_t B, int64
   const uint32_t nmask = uint32_t(N - 1);
   uint64_t y_off = 0, win_off = 0, ghat_off = 0, tw_off = 0;
   for (int m = 0; m < loops; ++m) {
+    if (alloc_should_fail()) throw std::bad_alloc();  // this iteration's host tables
     IterHost it{};
     IterDesc& d = it.d;
     // The vote keeps B and w in every loop; the iterative method halves B.
