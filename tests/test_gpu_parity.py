@@ -8,6 +8,14 @@ Tolerances:
     window table.
   * end to end: support bit-exact on noiseless signals; values within
     relative L2 1e-4 (FP32 and FP16-storage paths) or 1e-10 (FP64 path).
+    Beside every norm check, each coefficient on its own: |v_gpu - v_oracle|
+    / |v_oracle| <= 10x the norm tolerance.  A norm bound alone lets one
+    coefficient of K carry sqrt(K) times the budget; the per-coefficient
+    bound caps that at 10x, and the test prints the largest per-coefficient
+    error it saw.
+  * noisy inputs: every support mismatch is classified from the oracle's
+    trace as a near-tie (a decision within 1e-5 relative of its threshold,
+    or a collision with one) or unexplained; unexplained mismatches fail.
 """
 
 import math
@@ -17,6 +25,7 @@ import numpy as np
 import pytest
 
 import oracle.sfft_oracle as O
+from near_ties import classify, per_coefficient
 from paper_2011_05698_amd.signals import SignalSpec, make_signal
 
 torch = pytest.importorskip("torch")
@@ -47,6 +56,36 @@ def to_dev(x, dtype):
 
 def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def values_ok(gidx, gval, oidx, oval, tol):
+    """Values of the same support: rel-L2 <= tol and every coefficient within
+    10 tol of the oracle's (relative to its magnitude)."""
+    assert np.array_equal(gidx, oidx)
+    err = rel_l2(np.asarray(gval, dtype=np.complex128), oval)
+    pmax, pmed, _ = per_coefficient(gidx, np.asarray(gval, dtype=np.complex128), oidx, oval)
+    print(f"rel-L2 {err:.3g}; per-coefficient max {pmax:.3g}, median {pmed:.3g} over {len(oidx)}")
+    assert err <= tol, err
+    assert pmax <= 10 * tol, pmax
+    return err, pmax
+
+
+def noisy_ok(gidx, gval, oidx, oval, info, P, common_frac, tol):
+    """Noisy inputs: supports agree on at least common_frac, every mismatch is
+    a near-tie, and the common values agree within tol (rel-L2)."""
+    common = np.intersect1d(gidx, oidx)
+    cls = classify(gidx, gval, oidx, oval, info, P)
+    print(f"common {len(common)}/{len(oidx)}; near-ties {len(cls['near_tie'])}, "
+          f"unexplained {cls['unexplained']} margins {[cls['margins'][f] for f in cls['unexplained']]}")
+    assert len(common) >= common_frac * len(oidx), (len(common), len(oidx))
+    assert not cls["unexplained"], cls
+    gi = {f: v for f, v in zip(gidx, gval)}
+    oi = {f: v for f, v in zip(oidx, oval)}
+    a = np.array([gi[f] for f in common])
+    b = np.array([oi[f] for f in common])
+    pmax, _, _ = per_coefficient(common, a, common, b)
+    print(f"common values: rel-L2 {rel_l2(a, b):.3g}, per-coefficient max {pmax:.3g}")
+    assert rel_l2(a, b) <= tol
 
 
 def hash_bound(x, it, T, eps, N):
@@ -125,8 +164,7 @@ def test_execute_parity_noiseless(sf, case):
     gidx, gval, c = run_gpu(sf, plan, xd, scale)
     assert np.array_equal(oidx, np.sort(sup)), "oracle must recover the planted support"
     assert np.array_equal(gidx, oidx), f"support differs: {set(gidx) ^ set(oidx)}"
-    tol = 1e-10 if dt == "c128" else 1e-4
-    assert rel_l2(gval, oval) <= tol, rel_l2(gval, oval)
+    values_ok(gidx, gval, oidx, oval, 1e-10 if dt == "c128" else 1e-4)
 
 
 def test_recover_on_oracle_buckets(sf):
@@ -142,8 +180,7 @@ def test_recover_on_oracle_buckets(sf):
     torch.cuda.synchronize()
     c = int(cnt.item())
     oidx, oval, _ = O.sfft(x, P)
-    assert np.array_equal(idx[:c].cpu().numpy(), oidx)
-    assert rel_l2(val[:c].cpu().numpy().astype(np.complex128), oval) <= 1e-4
+    values_ok(idx[:c].cpu().numpy(), val[:c].cpu().numpy(), oidx, oval, 1e-4)
 
 
 def test_metric_shape_single_signal(sf):
@@ -157,28 +194,32 @@ def test_metric_shape_single_signal(sf):
     plan = sf.Plan(N, K, B, w, M, l, q, delta=delta, seed=602)
     gidx, gval, c = run_gpu(sf, plan, xd, scale)
     assert np.array_equal(oidx, np.sort(sup))
-    assert np.array_equal(gidx, oidx)
-    assert rel_l2(gval, oval) <= 1e-4
+    values_ok(gidx, gval, oidx, oval, 1e-4)
 
 
-def test_noisy_support_agreement(sf):
-    """20 dB noise (N = 2^20, K = 1000, B = 8192): decisions may flip at near
-    ties; the supports must still agree almost everywhere and the values of
-    the common support within FP32 noise of the oracle."""
-    N, K, B, w, M, l, q, delta = 2 ** 20, 1000, 8192, 163841, 12, 16, Fraction(1, 8), 1e-6
+SWEEP_LQ = [(l, q) for l in (2, 4, 16) for q in (Fraction(1, 2), Fraction(1, 4), Fraction(1, 8))]
+
+
+@pytest.mark.parametrize("l,q", SWEEP_LQ, ids=lambda v: str(v))
+def test_noisy_parameter_sweep(sf, l, q):
+    """The plain method at N = 2^20, K = 1000 planted plus 20 dB noise, B =
+    8192, w = 163841, 12 iterations, delta = 1e-6, complex64, for the nine
+    (multiscale, extension) pairs of the sweep mapped to the paper's
+    convergent (l, q) (l in {2, 4, 16} blocks, q in {1/2, 1/4, 1/8}).
+    Decisions may flip at near ties: the supports agree on at least 99%,
+    every mismatch is a near-tie of the oracle's trace, and the common
+    values agree within 1e-3 (noise makes them O(1e-1) away from truth but
+    both sides see the same noisy samples)."""
+    N, K, B, w, M, delta = 2 ** 20, 1000, 8192, 163841, 12, 1e-6
     x, sup, _ = make_signal(SignalSpec(N, K, 201, 20))
     xd, scale, xq = to_dev(x, "c64")
     P = O.make_plan(N, K, B, w, M, l, q, delta, seed=202)
-    oidx, oval, _ = O.sfft(xq, P)
+    oidx, oval, info = O.sfft(xq, P, trace=True)
     plan = sf.Plan(N, K, B, w, M, l, q, delta=delta, seed=202)
     gidx, gval, c = run_gpu(sf, plan, xd, scale)
-    common = np.intersect1d(gidx, oidx)
-    assert len(common) >= 0.99 * len(oidx), (len(common), len(oidx))
-    gi = {f: v for f, v in zip(gidx, gval)}
-    oi = {f: v for f, v in zip(oidx, oval)}
-    a = np.array([gi[f] for f in common])
-    b = np.array([oi[f] for f in common])
-    assert rel_l2(a, b) <= 1e-3
+    print(f"(l, q) = ({l}, {q}): R = {P.iters[0].R}, recall of the planted support "
+          f"{len(np.intersect1d(gidx, sup)) / K:.4f} (oracle {len(np.intersect1d(oidx, sup)) / K:.4f})")
+    noisy_ok(gidx, gval, oidx, oval, info, P, 0.99, 1e-3)
 
 
 @pytest.mark.parametrize("snr", [None, 30], ids=["noiseless", "snr30"])
@@ -192,19 +233,14 @@ def test_precision_form_shape(sf, snr):
     x, sup, _ = make_signal(SignalSpec(N, K, 301, snr))
     xd, scale, xq = to_dev(x, "c64")
     P = O.make_plan(N, K, B, w, M, l, q, delta, seed=302)
-    oidx, oval, _ = O.sfft(xq, P)
+    oidx, oval, info = O.sfft(xq, P, trace=snr is not None)
     plan = sf.Plan(N, K, B, w, M, l, q, delta=delta, seed=302, kahan=True)
     gidx, gval, c = run_gpu(sf, plan, xd, scale)
     if snr is None:
         assert np.array_equal(oidx, np.sort(sup))
-        assert np.array_equal(gidx, oidx)
-        assert rel_l2(gval, oval) <= 1e-4
+        values_ok(gidx, gval, oidx, oval, 1e-4)
     else:
-        common = np.intersect1d(gidx, oidx)
-        assert len(common) >= 0.99 * len(oidx), (len(common), len(oidx))
-        gi = {f: v for f, v in zip(gidx, gval)}
-        oi = {f: v for f, v in zip(oidx, oval)}
-        assert rel_l2(np.array([gi[f] for f in common]), np.array([oi[f] for f in common])) <= 1e-3
+        noisy_ok(gidx, gval, oidx, oval, info, P, 0.99, 1e-3)
 
 
 @pytest.mark.parametrize("snr,mags", [(None, "unit"), (40, "loguniform")], ids=["noiseless_unit", "snr40_loguniform"])
@@ -220,19 +256,14 @@ def test_large_bucket_count_f16(sf, snr, mags):
     x, sup, _ = make_signal(SignalSpec(N, K, 511, snr, mags=mags))
     xd, scale, xq = to_dev(x, "f16x2")
     P = O.make_plan(N, K, B, w, M, l, q, delta, seed=512)
-    oidx, oval, _ = O.sfft(xq, P)
+    oidx, oval, info = O.sfft(xq, P, trace=snr is not None)
     plan = sf.Plan(N, K, B, w, M, l, q, delta=delta, seed=512, dtype="f16x2")
     gidx, gval, c = run_gpu(sf, plan, xd, scale)
     if snr is None:
         assert np.array_equal(oidx, np.sort(sup))
-        assert np.array_equal(gidx, oidx)
-        assert rel_l2(gval, oval) <= 1e-4
+        values_ok(gidx, gval, oidx, oval, 1e-4)
     else:
-        common = np.intersect1d(gidx, oidx)
-        assert len(common) >= 0.98 * len(oidx), (len(common), len(oidx))
-        gi = {f: v for f, v in zip(gidx, gval)}
-        oi = {f: v for f, v in zip(oidx, oval)}
-        assert rel_l2(np.array([gi[f] for f in common]), np.array([oi[f] for f in common])) <= 1e-3
+        noisy_ok(gidx, gval, oidx, oval, info, P, 0.98, 1e-3)
 
 
 DIRECT = [
@@ -260,8 +291,7 @@ def test_direct_location_parity(sf, case):
     assert plan.iteration(0)["R"] == 1 and plan.iteration(0)["last_kind"] == 2
     gidx, gval, c = run_gpu(sf, plan, xd, scale)
     assert np.array_equal(oidx, np.sort(sup))
-    assert np.array_equal(gidx, oidx)
-    assert rel_l2(gval, oval) <= (1e-10 if dt == "c128" else 1e-4)
+    values_ok(gidx, gval, oidx, oval, 1e-10 if dt == "c128" else 1e-4)
 
 
 def test_direct_location_denser(sf):
@@ -310,8 +340,7 @@ def test_vote_parity(sf, case):
     assert all(plan.iteration(m)["B"] == B for m in range(M))
     gidx, gval, c = run_gpu(sf, plan, xd, scale)
     assert len(oidx) > 0
-    assert np.array_equal(gidx, oidx)
-    assert rel_l2(gval, oval) <= (1e-10 if dt == "c128" else 1e-4)
+    values_ok(gidx, gval, oidx, oval, 1e-10 if dt == "c128" else 1e-4)
 
 
 def test_vote_metric_shape(sf):
@@ -342,8 +371,7 @@ def test_vote_metric_shape(sf):
         oidx, oval, _ = O.sfft(x, P)
         c = int(cnt[s].item())
         assert c > 0.8 * K
-        assert np.array_equal(idx[s, :c].cpu().numpy(), oidx)
-        assert rel_l2(val[s, :c].cpu().numpy().astype(np.complex128), oval) <= 1e-4
+        values_ok(idx[s, :c].cpu().numpy(), val[s, :c].cpu().numpy(), oidx, oval, 1e-4)
 
 
 def test_batch_uneven_matches_single(sf):
@@ -370,8 +398,7 @@ def test_batch_uneven_matches_single(sf):
             gv = vals[s][:c].cpu().numpy()
             assert np.array_equal(gi, singles[s][0])
             assert np.array_equal(gv, singles[s][1].astype(np.complex64))
-            assert np.array_equal(gi, oracles[s][0])
-            assert rel_l2(gv.astype(np.complex128), oracles[s][1]) <= 1e-4
+            values_ok(gi, gv, oracles[s][0], oracles[s][1], 1e-4)
     # every fold launch shape sums the taps of a bucket in the same order, so
     # the tuned and the explicitly chosen shapes give bit-identical results
     best = batch.autotune()
@@ -450,9 +477,8 @@ def _check_position_major(sf, dtype, kahan, nsig, ld, location="multiscale", com
         oidx, oval, _ = O.sfft(xqs[s], O.make_plan(N, K, B, w, M, 16, 1, 1e-6, seed=900, location=location,
                                                    combine=combine))
         c = int(cnt[s].item())
-        assert np.array_equal(idx[s, :c].cpu().numpy(), oidx)
-        tol = 1e-10 if dtype == "c128" else 1e-4
-        assert rel_l2(val[s, :c].cpu().numpy().astype(np.complex128), oval) <= tol
+        values_ok(idx[s, :c].cpu().numpy(), val[s, :c].cpu().numpy(), oidx, oval,
+                  1e-10 if dtype == "c128" else 1e-4)
     with pytest.raises(sf.SfftError):
         sf.sfft_execute_interleaved(batch.handle, X, nsig - 1, scales, idx, val, cnt)
 
@@ -486,8 +512,7 @@ def test_position_major_metric_shape(sf):
     for s, x in xq.items():
         oidx, oval, _ = O.sfft(x, P)
         c = int(cnt[s].item())
-        assert np.array_equal(idx[s, :c].cpu().numpy(), oidx)
-        assert rel_l2(val[s, :c].cpu().numpy().astype(np.complex128), oval) <= 1e-4
+        values_ok(idx[s, :c].cpu().numpy(), val[s, :c].cpu().numpy(), oidx, oval, 1e-4)
 
 
 SMALLEST = [
@@ -508,8 +533,7 @@ def test_smallest_plans(sf, case):
     plan = sf.Plan(N, K, B, w, M, 16, 1.0, delta=1e-6, seed=ss + 1)
     gidx, gval, c = run_gpu(sf, plan, xd, scale)
     assert np.array_equal(oidx, np.sort(sup))
-    assert np.array_equal(gidx, oidx)
-    assert rel_l2(gval, oval) <= 1e-4
+    values_ok(gidx, gval, oidx, oval, 1e-4)
 
 
 def test_largest_signal_length(sf):
@@ -534,8 +558,7 @@ def test_largest_signal_length(sf):
     plan = sf.Plan(N, K, B, w, M, 16, 1.0, delta=1e-6, seed=77)
     gidx, gval, c = run_gpu(sf, plan, x, 1.0)
     order = np.argsort(freqs)
-    assert np.array_equal(gidx, np.array(freqs)[order])
-    assert rel_l2(gval, np.array(amps)[order]) <= 1e-4
+    values_ok(gidx, gval, np.array(freqs)[order], np.array(amps)[order], 1e-4)
     del x
     torch.cuda.empty_cache()
 
