@@ -153,6 +153,26 @@ sfft_status sfft_execute(sfft_plan_t p, const void* d_x, float scale, int64_t* d
                          int64_t* d_count, void* stream);
 
 /*
+ * sfft_execute_noalloc -- sfft_execute for callers that cannot allocate
+ * device memory while they run (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments, kernels and
+ * results as sfft_execute (bit for bit); the only difference is where the
+ * per-signal workspace lives: instead of the plan's own workspace, a static
+ * device array of 16 MiB that the library holds on every device it runs on
+ * until the process ends.  The call allocates nothing (no hipMalloc,
+ * hipFree or allocating library routine); its first call on a device looks
+ * up that device's array address once.
+ *   SFFT_ERR_CAPACITY  the plan's workspace (sfft_plan_info.workspace_bytes)
+ *                      exceeds 16 MiB; nothing is enqueued.
+ * Every call on one device shares that device's array, and the array keeps
+ * the last call's contents: two calls that overlap in time on one device
+ * (different streams, or different host threads without ordering) race and
+ * give undefined results.  Calls on one stream are ordered and safe.
+ */
+sfft_status sfft_execute_noalloc(sfft_plan_t p, const void* d_x, float scale, int64_t* d_idx, void* d_val,
+                                 int64_t* d_count, void* stream);
+
+/*
  * sfft_hash_to_bins -- HashToBins alone (Sec. 2.4, Lemma 1, Eq. 13) for all
  * iterations and rounds of the plan, without subtraction:
  *   d_yhat[off_m + j*B_m + i] = (1/N) sum_b y_{m,j}[b] exp(-2 pi i i b / B_m),

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -38,6 +39,36 @@ static hipError_t dev_malloc(void** p, size_t bytes) {
   return hipMalloc(p, bytes);
 }
 
+}  // namespace sfft
+
+// Workspace of sfft_execute_noalloc: one static array per device, held until
+// the process ends.  Host code never passes the array's name to a kernel (on
+// the host it is only a stand-in for the symbol); it takes the device address
+// from hipGetSymbolAddress once per device and uses that address.
+namespace sfft {
+constexpr size_t kScratchBytes = size_t(16) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::once_flag g_scratch_once[kMaxDevices];
+static void* g_scratch_ptr[kMaxDevices];
+static hipError_t g_scratch_err[kMaxDevices];
+
+// Device address of the current device's scratch array (nullptr and *err on failure).
+static void* scratch_address(hipError_t* err) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    *err = e != hipSuccess ? e : hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::call_once(g_scratch_once[dev], [dev] {
+    void* ptr = nullptr;
+    g_scratch_err[dev] = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    g_scratch_ptr[dev] = g_scratch_err[dev] == hipSuccess ? ptr : nullptr;
+  });
+  *err = g_scratch_err[dev];
+  return g_scratch_ptr[dev];
+}
 }  // namespace sfft
 
 struct sfft_plan_s {
@@ -413,6 +444,33 @@ sfft_status sfft_execute(sfft_plan_t p, const void* d_x, float scale, int64_t* d
   if (st != SFFT_OK) return st;
   int e = launch_recover(p->hp.dtype, a, 1, s);
   if (e != hipSuccess) return hip_fail(hipError_t(e), "recover launch");
+  return SFFT_OK;
+}
+
+sfft_status sfft_execute_noalloc(sfft_plan_t p, const void* d_x, float scale, int64_t* d_idx, void* d_val,
+                                 int64_t* d_count, void* stream) {
+  sfft_status st = check_plan(p);
+  if (st != SFFT_OK) return st;
+  if (!d_x || !d_idx || !d_val || !d_count) return fail(SFFT_ERR_PARAM, "null buffer");
+  if (p->hp.desc.ws_bytes > kScratchBytes)
+    return fail(SFFT_ERR_CAPACITY, "plan workspace of " + std::to_string(p->hp.desc.ws_bytes) +
+                                       " bytes exceeds the static scratch of " + std::to_string(kScratchBytes) +
+                                       " bytes");
+  hipError_t e = hipSuccess;
+  unsigned char* ws = static_cast<unsigned char*>(scratch_address(&e));
+  if (!ws) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+  // every workspace word the kernels read is written first in the same call
+  // (bucket values by the fold and the DFT, the store and its index by the
+  // recovery's own initialization), so nothing is cleared here
+  SignalDesc sd = make_signal(p, d_x, scale, nullptr, d_idx, d_val, d_count);
+  sd.ws = ws;
+  sd.y = ws + p->hp.desc.off_y;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const SigArg a = single(sd);
+  st = run_hash(p, a, s);
+  if (st != SFFT_OK) return st;
+  int le = launch_recover(p->hp.dtype, a, 1, s);
+  if (le != hipSuccess) return hip_fail(hipError_t(le), "recover launch");
   return SFFT_OK;
 }
 

@@ -24,7 +24,7 @@ SFFT_PLAN_HOST_ONLY = 1
 MAX_ROUNDS = 48
 
 EXPORTED = [
-    "sfft_default_options", "sfft_plan", "sfft_execute", "sfft_hash_to_bins", "sfft_recover",
+    "sfft_default_options", "sfft_plan", "sfft_execute", "sfft_execute_noalloc", "sfft_hash_to_bins", "sfft_recover",
     "sfft_get_plan_info", "sfft_get_iter_info", "sfft_plan_dump_tables", "sfft_destroy",
     "sfft_batch_create", "sfft_execute_batch", "sfft_batch_launch_stage", "sfft_batch_destroy",
     "sfft_batch_create_interleaved", "sfft_execute_interleaved", "sfft_plan_set_fold_config", "sfft_batch_set_fold_config", "sfft_batch_autotune", "sfft_status_string",
@@ -96,6 +96,7 @@ def _load():
         "sfft_default_options": (None, [ctypes.POINTER(Options)]),
         "sfft_plan": (i32, [ctypes.POINTER(vp), i64, i64, i64, i64, i32, i32, f64, ctypes.POINTER(Options)]),
         "sfft_execute": (i32, [vp, vp, f32, vp, vp, vp, vp]),
+        "sfft_execute_noalloc": (i32, [vp, vp, f32, vp, vp, vp, vp]),
         "sfft_hash_to_bins": (i32, [vp, vp, f32, vp, vp]),
         "sfft_recover": (i32, [vp, vp, vp, vp, vp, vp]),
         "sfft_get_plan_info": (i32, [vp, ctypes.POINTER(PlanInfo)]),
@@ -159,6 +160,11 @@ def sfft_plan(N, K, B, w, loops, multiscale, extension, opt: Options | None = No
 
 def sfft_execute(plan, x, scale, idx, val, count, stream=None):
     _check(_lib.sfft_execute(plan, _ptr(x), float(scale), _ptr(idx), _ptr(val), _ptr(count), _stream(stream)))
+
+
+def sfft_execute_noalloc(plan, x, scale, idx, val, count, stream=None):
+    _check(_lib.sfft_execute_noalloc(plan, _ptr(x), float(scale), _ptr(idx), _ptr(val), _ptr(count),
+                                     _stream(stream)))
 
 
 def sfft_hash_to_bins(plan, x, scale, yhat, stream=None):
