@@ -44,14 +44,15 @@ struct PlanDesc {
   uint32_t Bmax;                  // largest B_m
   uint32_t sort_cap;              // power of two >= max(rec_cap, Bmax)
   uint32_t fp64_phase;            // take location phases in FP64 (N >= 2^24)
-  uint32_t log_hcap;              // hash index of the store: 2^log_hcap >= 2 rec_cap slots
+  uint32_t Rmax;                  // largest R_m
+  uint32_t max_slots;             // largest reach_m + 1
   uint32_t location;              // sfft_location of every iteration
   uint32_t combine;               // sfft_combine
   uint64_t y_total;               // complex elements of bucket values per signal
   uint64_t ws_bytes;              // workspace bytes per signal
   // byte offsets inside one signal's workspace
-  uint64_t off_y, off_recf, off_recv, off_htkey, off_htidx, off_candu, off_candd, off_candv;
-  uint64_t off_keys, off_p0;
+  uint64_t off_y, off_recf, off_recv;
+  uint64_t off_work, work_bytes;  // the recovery's arrays that do not fit in LDS
   uint64_t off_nvote, off_votes;  // vote: loops that located each store entry, and their estimates
   double eta, rho;
   const IterDesc* iters;          // device array of M descriptors
@@ -124,6 +125,21 @@ sfft_status build_host_plan(HostPlan& hp, int64_t N, int64_t K, int64_t B, int64
 
 // Workspace layout of one signal (fills the off_* fields of desc).
 void layout_workspace(HostPlan& hp);
+
+// Bytes of the recovery's work area (arrays of one iteration that do not fit
+// in LDS, or the final top-K keys), for any iteration of the plan: every
+// array at its largest size, each rounded up to 16 bytes.  cb and rb are the
+// sizes of one complex and one real value.
+inline uint64_t recover_work_bytes(const PlanDesc& pd, uint64_t cb, uint64_t rb) {
+  const uint64_t a = 16 * 24;
+  const uint64_t rc = pd.rec_cap, bm = pd.Bmax, sc = pd.sort_cap;
+  const uint64_t store = sc * 4 + rc * (8 + cb) + rc * (4 + cb + 8);  // cells, keys, values; sort temporaries
+  const uint64_t bucket = bm * (cb + 4) + bm * 8 + bm * 8;           // round 0, located u; runs; power keys
+  const uint64_t cand = bm * (4 + 4) + uint64_t(pd.Rmax) * bm * (cb + 8) + bm * cb;  // lists, rows, angles, values
+  const uint64_t iter = a + store + rc * pd.max_slots * rb + bucket + cand;
+  const uint64_t topk = a + sc * (16 + 4);
+  return iter > topk ? iter : topk;
+}
 
 void set_last_error(const std::string& s);
 

@@ -263,9 +263,10 @@ sfft_status build_host_plan(HostPlan& hp, int64_t N, int64_t K, int64_t B, int64
   while (sc < std::max(cap, bm)) sc <<= 1;
   pd.sort_cap = uint32_t(sc);
   pd.fp64_phase = N >= (int64_t(1) << 24) ? 1u : 0u;
-  uint32_t lh = 1;
-  while ((uint64_t(1) << lh) < 2 * cap) ++lh;
-  pd.log_hcap = lh;
+  for (auto& it : hp.iters) {
+    pd.Rmax = std::max(pd.Rmax, it.d.R);
+    pd.max_slots = std::max(pd.max_slots, it.d.reach + 1);
+  }
   pd.y_total = y_off;
   pd.eta = opt.eta;
   pd.rho = opt.rho;
@@ -285,17 +286,8 @@ void layout_workspace(HostPlan& hp) {
   pd.off_y = take(pd.y_total * 2 * rs);
   pd.off_recf = take(uint64_t(pd.rec_cap) * 4);
   pd.off_recv = take(uint64_t(pd.rec_cap) * 2 * rs);
-  pd.off_htkey = take((uint64_t(1) << pd.log_hcap) * 4);
-  pd.off_htidx = take((uint64_t(1) << pd.log_hcap) * 4);
-  pd.off_candu = take(uint64_t(pd.Bmax) * 4);
-  pd.off_candd = take(uint64_t(pd.Bmax) * 4);
-  pd.off_candv = take(uint64_t(pd.Bmax) * 2 * rs);
-  // subtraction scratch when it does not fit in LDS (cell ends, keys, values, window
-  // weights per reachable bucket, one round's values, run bounds and bucket sums), or top-K keys
-  uint64_t max_slots = 1;
-  for (auto& it : hp.iters) max_slots = std::max<uint64_t>(max_slots, uint64_t(it.d.reach) + 1);
-  pd.off_keys = take(uint64_t(pd.sort_cap) * (4 + 8 + 16 + 8 * max_slots + 16) + uint64_t(pd.Bmax) * 24 + 512);
-  pd.off_p0 = take(uint64_t(pd.Bmax) * rs);
+  pd.work_bytes = recover_work_bytes(pd, 2 * rs, rs);
+  pd.off_work = take(pd.work_bytes);
   const bool vote = pd.combine == SFFT_COMBINE_VOTE;
   pd.off_nvote = take(vote ? uint64_t(pd.rec_cap) * 4 : 0);
   pd.off_votes = take(vote ? uint64_t(pd.rec_cap) * pd.M * 2 * rs : 0);

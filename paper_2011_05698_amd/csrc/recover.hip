@@ -7,23 +7,39 @@
 // Under the vote over loops (SFFT_COMBINE_VOTE) no loop subtracts; a store
 // entry keeps one estimate per loop that located it, and the entries that at
 // least half of the loops located take the median of their estimates.
-// One thread per bucket for the per-bucket work.  The recovered store is an
-// append-only array with an open-addressing hash index on the frequency, so an
-// iteration's survivors go straight in; every sum that depends on the store's
-// order (per-bucket subtraction, top-K) is taken in frequency order, so results
-// are bit-reproducible.  No private (scratch) arrays; wave-level scans and an
-// LDS radix select keep the number of workgroup barriers low.
+//
+// Work per iteration, in the order the decisions need it:
+//   1. the store, read once from memory, is sorted by its permuted frequency
+//      u = sigma f mod N (a counting sort on the top bits of u); the
+//      coefficients that leak into bucket i are then one circular run of
+//      that order;
+//   2. round 0 of every bucket, minus its run's contributions;
+//   3. the detection threshold from round 0 alone (median and maximum of
+//      |yhat_0|^2): only buckets above it can be detected, so
+//   4. rounds 1..R are formed (bucket values minus their runs) for those
+//      candidate buckets only;
+//   5. per (candidate, round): the phase difference theta_j as a binary angle
+//      and the round-to-round magnitude test;
+//   6. per consistent candidate: location, verification and the median
+//      estimate, from values and angles already in LDS;
+//   7. dedupe and accumulation: a located position is looked up in the
+//      sorted store (no hash index), existing entries are updated, new ones
+//      appended.
+// Every sum over the store is taken in u order by a team of lanes closed by a
+// fixed cross-lane butterfly, so results are bit-reproducible: repeated runs,
+// batches and single calls agree.  The arrays of an iteration live in LDS
+// while it has room and in the signal's work area otherwise.
 #include "device_common.h"
 
 namespace sfft {
 
 constexpr int kRecThreads = 256;    // 4 waves; the radix select assumes >= 256
 constexpr int kWaves = kRecThreads / 64;
-constexpr int kLdsBytes = 75776;    // one buffer, reused phase by phase; two workgroups still fit a CU
+constexpr uint32_t kLdsBytes = 78848;  // with the static arrays, two workgroups fit a CU (160 KiB)
 constexpr uint32_t kNone = 0xFFFFFFFFu;
-constexpr int kRegRounds = 16;      // rounds whose estimates are sorted in registers
-constexpr int kVgBatch = 4;         // entries whose loads a thread issues together
-constexpr int kMaxRoundsPerPass = 4; // rounds the subtraction handles in one pass when LDS allows
+constexpr int kRegRounds = 8;       // rounds whose estimates are sorted in registers
+constexpr int kBatch = 4;           // independent loads a thread issues together
+constexpr int kBatchY = 8;          // ... for the candidates' bucket values
 
 struct K128 {
   uint64_t hi, lo;
@@ -34,9 +50,10 @@ __device__ __forceinline__ bool key_less(const K128& a, const K128& b) {
   return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo);
 }
 
-// Ascending bitonic sort of n keys (n a power of two) by the whole block.
+// Ascending bitonic sort of n keys (n a power of two) with a 32-bit payload
+// that moves with its key, by the whole block.
 template <typename Key>
-__device__ void block_bitonic_sort(Key* keys, uint32_t n) {
+__device__ void block_bitonic_sort(Key* keys, uint32_t* pay, uint32_t n) {
   for (uint32_t k = 2; k <= n; k <<= 1) {
     for (uint32_t j = k >> 1; j > 0; j >>= 1) {
       for (uint32_t p = threadIdx.x; p < n / 2; p += blockDim.x) {
@@ -47,6 +64,9 @@ __device__ void block_bitonic_sort(Key* keys, uint32_t n) {
         if (up ? key_less(b, a) : key_less(a, b)) {
           keys[i] = b;
           keys[ixj] = a;
+          const uint32_t t = pay[i];
+          pay[i] = pay[ixj];
+          pay[ixj] = t;
         }
       }
       __syncthreads();
@@ -177,17 +197,6 @@ __device__ V block_max(V v, V* sh) {
   return r;
 }
 
-template <typename V>
-__device__ V block_min(V v, V* sh) {
-  v = wave_min(v);
-  if ((threadIdx.x & 63) == 63) sh[threadIdx.x >> 6] = v;
-  __syncthreads();
-  V r = sh[0];
-  for (uint32_t w = 1; w < blockDim.x / 64; ++w) r = sh[w] < r ? sh[w] : r;
-  __syncthreads();
-  return r;
-}
-
 __device__ uint32_t block_sum(uint32_t v, uint32_t* sh) {
   v = team_sum(v, 64u);
   if ((threadIdx.x & 63) == 63) sh[threadIdx.x >> 6] = v;
@@ -198,35 +207,75 @@ __device__ uint32_t block_sum(uint32_t v, uint32_t* sh) {
   return r;
 }
 
-// The k-th smallest (0-based) of n unsigned keys, by most-significant-digit
-// radix selection (8-bit digits); the block must have at least 256 threads.
+// The k-th smallest (0-based) of n unsigned keys, and the next one in order
+// (the (k+1)-th; equal to the k-th when that value repeats), by most-
+// significant-digit radix selection with 8-bit digits.  Per digit: the
+// keys that match the prefix so far add into a histogram, and wave 0 alone
+// scans it, picks the digit that holds rank k and clears the other
+// histogram for the next digit: two barriers per digit.  hist holds 2 x 256
+// counters and must be zero on entry; it is zero again on return.
 template <typename K>
-__device__ K block_select(const K* keys, uint32_t n, uint32_t k, uint32_t* hist, uint32_t* wsum, uint32_t* sel) {
+__device__ void block_select2(const K* keys, uint32_t n, uint32_t k, uint32_t* hist, uint32_t* sel,
+                              uint32_t* wsum, K* red, K* out_k, K* out_k1) {
   K prefix = 0, mask = 0;
   uint32_t r = k;
+  int cur = 0;
   for (int shift = int(sizeof(K) * 8) - 8; shift >= 0; shift -= 8) {
-    if (threadIdx.x < 256) hist[threadIdx.x] = 0;
-    __syncthreads();
+    uint32_t* h = hist + cur * 256;
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
       const K key = keys[i];
-      if ((key & mask) == prefix) atomicAdd(&hist[uint32_t(key >> shift) & 255u], 1u);
+      if ((key & mask) == prefix) atomicAdd(&h[uint32_t(key >> shift) & 255u], 1u);
     }
     __syncthreads();
-    const uint32_t c = threadIdx.x < 256 ? hist[threadIdx.x] : 0u;
-    uint32_t total;
-    const uint32_t before = block_excl_scan(c, wsum, &total);
-    if (threadIdx.x < 256 && before <= r && r < before + c) {
-      sel[0] = threadIdx.x;
-      sel[1] = r - before;
+    if (threadIdx.x < 64) {
+      const uint32_t l = threadIdx.x;
+      const uint32_t c0 = h[4 * l], c1 = h[4 * l + 1], c2 = h[4 * l + 2], c3 = h[4 * l + 3];
+      const uint32_t tot = c0 + c1 + c2 + c3;
+      const uint32_t before = wave_incl_scan(tot) - tot;
+      if (before <= r && r < before + tot) {
+        uint32_t b = before, d = 4 * l;
+        if (r >= b + c0) { b += c0; ++d;
+          if (r >= b + c1) { b += c1; ++d;
+            if (r >= b + c2) { b += c2; ++d; } } }
+        sel[0] = d;
+        sel[1] = r - b;
+      }
+      uint32_t* other = hist + (cur ^ 1) * 256;
+      other[4 * l] = 0; other[4 * l + 1] = 0; other[4 * l + 2] = 0; other[4 * l + 3] = 0;
     }
     __syncthreads();
-    const uint32_t d = sel[0];
-    r = sel[1];
-    __syncthreads();
-    prefix |= K(d) << shift;
+    prefix |= K(sel[0]) << shift;
     mask |= K(255) << shift;
+    r = sel[1];
+    cur ^= 1;
   }
-  return prefix;
+  // the k-th is `prefix`; the (k+1)-th is the same value if more than k+1
+  // keys are <= it, else the smallest key above it
+  uint32_t le = 0;
+  K above = ~K(0);
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const K key = keys[i];
+    le += key <= prefix ? 1u : 0u;
+    if (key > prefix && key < above) above = key;
+  }
+  le = team_sum(le, 64u);
+  above = wave_min(above);
+  if ((threadIdx.x & 63) == 63) {
+    wsum[threadIdx.x >> 6] = le;
+    red[threadIdx.x >> 6] = above;
+  }
+  // the histogram used by the last digit is cleared for the next call
+  if (threadIdx.x < 256) hist[(cur ^ 1) * 256 + threadIdx.x] = 0;
+  __syncthreads();
+  uint32_t tle = 0;
+  K ab = ~K(0);
+  for (uint32_t w = 0; w < blockDim.x / 64; ++w) {
+    tle += wsum[w];
+    ab = red[w] < ab ? red[w] : ab;
+  }
+  __syncthreads();
+  *out_k = prefix;
+  *out_k1 = tle >= k + 2 ? prefix : ab;
 }
 
 // The run of sorted store entries that reach one bucket.
@@ -247,35 +296,50 @@ __device__ __forceinline__ int64_t first_bucket(uint32_t u, uint32_t D, uint32_t
   return -((int64_t(D) - int64_t(u)) >> logL);
 }
 
-// Hash index of the recovered store: frequency -> entry, linear probing.
-// Keys are read with L1-bypassing atomic loads (slots are claimed by atomics).
-__device__ __forceinline__ uint32_t hslot(uint32_t f, uint32_t logh) { return (f * 0x9E3779B1u) >> (32 - logh); }
-__device__ __forceinline__ uint32_t hkey(const uint32_t* hk, uint32_t h) {
-  return __hip_atomic_load(hk + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ uint32_t ht_find(const uint32_t* hk, const uint32_t* hi, uint32_t f, uint32_t logh) {
-  const uint32_t m = (1u << logh) - 1;
-  uint32_t h = hslot(f, logh);
-  for (uint32_t probe = 0; probe <= m; ++probe) {
-    const uint32_t k = hkey(hk, h);
-    if (k == f) return hi[h];
-    if (k == kNone) return kNone;
-    h = (h + 1) & m;
+// Work area of one iteration: a stack over the workgroup's LDS buffer that
+// places an array in the signal's work region (at its own offset there)
+// once LDS has no room left.  Every thread computes the same layout.
+struct Arena {
+  unsigned char* lds;
+  unsigned char* glob;
+  uint32_t lds_top;
+  uint64_t glob_top;
+  struct Mark {
+    uint32_t l;
+    uint64_t g;
+  };
+  __device__ Mark mark() const { return Mark{lds_top, glob_top}; }
+  __device__ void release(Mark m) {
+    lds_top = m.l;
+    glob_top = m.g;
   }
-  return kNone;
-}
+  template <typename T>
+  __device__ T* take(uint64_t count) {
+    const uint64_t bytes = (count * sizeof(T) + 15) & ~uint64_t(15);
+    if (uint64_t(lds_top) + bytes <= kLdsBytes) {
+      T* p = reinterpret_cast<T*>(lds + lds_top);
+      lds_top += uint32_t(bytes);
+      return p;
+    }
+    T* p = reinterpret_cast<T*>(glob + glob_top);
+    glob_top += bytes;
+    return p;
+  }
+};
 
-// Circular distance between two binary angles (2^64 = one turn).
-__device__ __forceinline__ uint64_t angle_dist(uint64_t a, uint64_t b) {
-  const uint64_t d = a - b, e = b - a;
+// ---- binary angles: one turn = 2^32 (uint32_t) or 2^64 (uint64_t) ----
+template <typename A>
+__device__ __forceinline__ A angle_dist(A a, A b) {
+  const A d = a - b, e = b - a;
   return d < e ? d : e;
 }
 
 // theta_j = arg(yhat_0 conj(yhat_j)), the two-round phase difference of
 // Eq. 15-16 (sign read so that theta_j = 2 pi (tau_j u mod N) / N for a lone
-// coefficient at permuted position u), as a binary angle.
-template <typename R>
-__device__ __forceinline__ uint64_t theta_bin(cplx<R> y0, cplx<R> yj, bool fp64) {
+// coefficient at permuted position u), as a binary angle: the angle in
+// turns, times 2^32 or 2^64, truncated.
+template <typename A, typename R>
+__device__ __forceinline__ A theta_bin(cplx<R> y0, cplx<R> yj, bool fp64) {
   double turns;
   if (fp64 || sizeof(R) == 8) {
     const double zr = double(y0.re) * double(yj.re) + double(y0.im) * double(yj.im);
@@ -287,91 +351,118 @@ __device__ __forceinline__ uint64_t theta_bin(cplx<R> y0, cplx<R> yj, bool fp64)
     turns = double(atan2f(zi, zr) * 0.159154943f);
   }
   if (turns < 0.0) turns += 1.0;
-  const double t64 = turns * 18446744073709551616.0;
-  if (!(t64 < 18446744073709551616.0) || !(t64 >= 0.0)) return 0;
-  return uint64_t(t64);
+  constexpr double kTurn = sizeof(A) == 8 ? 18446744073709551616.0 : 4294967296.0;
+  const double t = turns * kTurn;
+  if (!(t < kTurn) || !(t >= 0.0)) return 0;
+  return A(t);
 }
 
-// Phase of position p seen through multiplier tau: (p tau mod N) / N turns.
-__device__ __forceinline__ uint64_t pos_angle(uint64_t p, uint64_t tau, uint32_t logN) {
-  return ((p * tau) & ((uint64_t(1) << logN) - 1)) << (64 - logN);
+// Index k < n of the angle first + k step nearest to t (the smallest index on
+// a tie), with four independent running minima (k = 0, 1, 2, 3 mod 4) so
+// that the comparisons of consecutive candidates do not wait on each other.
+template <typename A>
+__device__ __forceinline__ uint32_t argmin_progression(A first, A step, uint32_t n, A t) {
+  A bd[4] = {~A(0), ~A(0), ~A(0), ~A(0)};
+  uint32_t bk[4] = {0, 1, 2, 3};
+  A cur[4] = {first, first + step, first + 2 * step, first + 3 * step};
+  const A step4 = 4 * step;
+  uint32_t k = 0;
+  for (; k + 4 <= n; k += 4) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const A d = angle_dist(cur[r], t);
+      if (d < bd[r]) {
+        bd[r] = d;
+        bk[r] = k + uint32_t(r);
+      }
+      cur[r] += step4;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {  // the n mod 4 remaining candidates
+    if (k + uint32_t(r) < n) {
+      const A d = angle_dist(cur[r], t);
+      if (d < bd[r]) {
+        bd[r] = d;
+        bk[r] = k + uint32_t(r);
+      }
+    }
+  }
+  A best_d = bd[0];
+  uint32_t best_k = bk[0];
+#pragma unroll
+  for (int r = 1; r < 4; ++r) {
+    if (bd[r] < best_d || (bd[r] == best_d && bk[r] < best_k)) {
+      best_d = bd[r];
+      best_k = bk[r];
+    }
+  }
+  return best_k;
 }
 
-// Multiscale location (Sec. 3.2) of the lone coefficient of bucket i and its
-// verification.  Returns kNone if rejected, else u; *dist = |iL - u|_N.
-template <typename R>
-__device__ uint32_t locate_bucket(const PlanDesc* pd, const IterDesc* it, const cplx<R>* Y, uint32_t i,
-                                  uint32_t* dist) {
-  const uint32_t B = it->B, L = it->L, R_ = it->R, logN = pd->logN, nmask = pd->N - 1;
-  const bool fp64 = pd->fp64_phase != 0;
-  const cplx<R> y0 = Y[i];
+// Multiscale location (Sec. 3.2) of the lone coefficient of a candidate
+// bucket i, from its binary angles th(j), j = 1..R, and its verification.
+// Returns kNone if rejected, else u; *dist = |iL - u|_N.
+//   block step: the centre of block b of the region [a, a + len) is
+//     a + (b + 1/2) len / l, whose phase is ((2 l a + (2b+1) len) tau mod 2lN)
+//     / 2lN turns: an exact integer fraction that grows by 2 len tau per
+//     block; the nearest block wins (the smaller on a tie) and the region
+//     restarts q/2 blocks before it (floor);
+//   last step: the position of the region nearest in phase (the smaller on
+//     a tie);
+//   verification: within reach D of the bucket centre, and every round's
+//     phase within pi / l of the located position (the Eq. 18 bound).
+// A = uint32_t needs 2lN <= 2^32 (block-centre phases exact in 32 bits).
+template <typename A, typename TH>
+__device__ uint32_t locate_bucket(const PlanDesc* pd, const IterDesc* it, uint32_t i, TH th, uint32_t* dist) {
+  constexpr uint32_t kBits = sizeof(A) * 8;
+  const uint32_t L = it->L, R_ = it->R, logN = pd->logN, nmask = pd->N - 1;
   const uint32_t l = pd->l, logM2 = 1 + pd->logl + logN;
   const uint64_t m2mask = (uint64_t(1) << logM2) - 1;
-  const uint32_t sh = 64 - logM2;
   const uint32_t den_shift = 1 + pd->logqd + pd->logl;
   const int64_t qd = int64_t(1) << pd->logqd, qn = pd->qn;
   int64_t a = int64_t(i) * L - int64_t(L / 2) - int64_t(it->e);
   uint32_t u = 0;
   if (pd->location == SFFT_LOCATE_DIRECT) {
     // two rounds, tau_1 = 1: theta_1 = 2 pi u / N; the nearest position,
-    // halves rounded up (floor(2 theta N) + 1) / 2 on the binary angle
-    const uint64_t th = theta_bin(y0, Y[size_t(B) + i], fp64);
-    u = uint32_t(((th >> (63 - logN)) + 1) >> 1) & nmask;
-  }
-  for (uint32_t j = 1; j <= R_ && pd->location != SFFT_LOCATE_DIRECT; ++j) {
-    const uint64_t th = theta_bin(y0, Y[size_t(j) * B + i], fp64);
-    const uint64_t len = it->len[j], tau = it->tau[j];
-    if (j < R_) {
-      // block step: the centre of block b is a + (b + 1/2) len / l; its phase
-      // is ((2 l a + (2b+1) len) tau mod 2lN) / 2lN turns
-      const uint64_t A = uint64_t(int64_t(2 * l) * a);
-      uint32_t best_b = 0;
-      uint64_t best_d = ~uint64_t(0);
-      for (uint32_t b = 0; b < l; ++b) {
-        const uint64_t num = ((A + uint64_t(2 * b + 1) * len) * tau) & m2mask;
-        const uint64_t d = angle_dist(num << sh, th);
-        if (d < best_d) {
-          best_d = d;
-          best_b = b;
-        }
+    // halves rounded up: (floor(2 theta N) + 1) / 2 on the binary angle
+    u = uint32_t(((uint64_t(th(1)) >> (kBits - 1 - logN)) + 1) >> 1) & nmask;
+  } else {
+    for (uint32_t j = 1; j <= R_; ++j) {
+      const A t = th(j);
+      const uint64_t len = it->len[j], tau = it->tau[j];
+      if (j < R_) {
+        const uint64_t base = ((uint64_t(int64_t(2 * l) * a) + len) * tau) & m2mask;
+        const A step = A(((2 * len * tau) & m2mask) << (kBits - logM2));
+        const uint32_t best_b = argmin_progression<A>(A(base << (kBits - logM2)), step, l, t);
+        a += ((2 * int64_t(best_b) * qd - qn) * int64_t(len)) >> den_shift;
+      } else {
+        const A step = A((tau & nmask) << (kBits - logN));
+        const A first = A(((uint64_t(a) * tau) & nmask) << (kBits - logN));
+        const int64_t best_c = a + int64_t(argmin_progression<A>(first, step, uint32_t(len), t));
+        u = uint32_t(uint64_t(best_c) & nmask);
       }
-      // the new region starts q/2 blocks before the chosen block (floor)
-      a += ((2 * int64_t(best_b) * qd - qn) * int64_t(len)) >> den_shift;
-    } else {
-      // last step: the position of the region closest in phase
-      int64_t best_c = a;
-      uint64_t best_d = ~uint64_t(0);
-      for (uint64_t c = 0; c < len; ++c) {
-        const uint64_t d = angle_dist(pos_angle(uint64_t(a + int64_t(c)), tau, logN), th);
-        if (d < best_d) {
-          best_d = d;
-          best_c = a + int64_t(c);
-        }
-      }
-      u = uint32_t(uint64_t(best_c) & nmask);
     }
   }
-  // verification: within reach of the bucket centre, and every round's
-  // phase within pi / l of the located position (the Eq. 18 bound)
   const uint32_t d1 = (i * L - u) & nmask;
   const uint32_t dd = min(d1, pd->N - d1);
   if (dd > it->D) return kNone;
-  const uint64_t tol = uint64_t(1) << (63 - pd->logl);
+  const A tol = A(1) << (kBits - 1 - pd->logl);
   for (uint32_t j = 1; j <= R_; ++j) {
-    const uint64_t th = theta_bin(y0, Y[size_t(j) * B + i], fp64);
-    if (angle_dist(pos_angle(u, it->tau[j], logN), th) > tol) return kNone;
+    const A pos = A((uint64_t((u * it->tau[j]) & nmask)) << (kBits - logN));
+    if (angle_dist(pos, th(j)) > tol) return kNone;
   }
   *dist = dd;
   return u;
 }
 
-// Round-j estimate of the coefficient at permuted position u in bucket i
-// (Eq. 14): yhat_j[i] exp(+2 pi i T_j u / N) / Ghat.
+// Round-j estimate of the coefficient at permuted position u (Eq. 14) before
+// the division by Ghat: yhat_j exp(+2 pi i T_j u / N).  Dividing every
+// round by the same Ghat does not change which rounds are the middle ones,
+// so the median is divided once, afterwards.
 template <typename R>
-__device__ __forceinline__ cplx<R> round_estimate(const cplx<R>* Y, uint32_t B, uint32_t i, uint32_t j,
-                                                   uint32_t Tj, uint32_t u, uint32_t nmask, uint32_t logN, R g) {
-  const cplx<R> e = cmul(Y[size_t(j) * B + i], expi<R>((Tj * u) & nmask, logN, R(1)));
-  return {e.re / g, e.im / g};
+__device__ __forceinline__ cplx<R> round_estimate(cplx<R> y, uint32_t Tj, uint32_t u, uint32_t nmask, uint32_t logN) {
+  return cmul(y, expi<R>((Tj * u) & nmask, logN, R(1)));
 }
 
 template <typename R>
@@ -412,16 +503,15 @@ __device__ __forceinline__ R pick_median(const R (&v)[NR], uint32_t n) {
 }
 
 // Median over the R+1 rounds, real and imaginary parts separately; the mean
-// of the two middle values for an even count.
-// The R+1 round estimates sorted in registers (a network of NR >= R+1).
-template <int NR, typename R>
-__device__ __forceinline__ cplx<R> median_in_regs(const cplx<R>* Y, const IterDesc* it, uint32_t i, uint32_t u,
-                                                  uint32_t nmask, uint32_t logN, R g, uint32_t n) {
+// of the two middle values for an even count.  yv(j) gives round j's value.
+template <int NR, typename R, typename YV>
+__device__ __forceinline__ cplx<R> median_in_regs(YV yv, const IterDesc* it, uint32_t u, uint32_t nmask,
+                                                  uint32_t logN, uint32_t n) {
   R vr[NR], vi[NR];
 #pragma unroll
   for (int j = 0; j < NR; ++j) {
     if (uint32_t(j) < n) {
-      const cplx<R> e = round_estimate(Y, it->B, i, uint32_t(j), it->T[j], u, nmask, logN, g);
+      const cplx<R> e = round_estimate<R>(yv(uint32_t(j)), it->T[j], u, nmask, logN);
       vr[j] = e.re;
       vi[j] = e.im;
     } else {
@@ -434,22 +524,18 @@ __device__ __forceinline__ cplx<R> median_in_regs(const cplx<R>* Y, const IterDe
   return {pick_median<NR>(vr, n), pick_median<NR>(vi, n)};
 }
 
-// Median over the R+1 rounds, real and imaginary parts separately; the mean
-// of the two middle values for an even count.
-template <typename R>
-__device__ cplx<R> median_estimate(const cplx<R>* Y, const IterDesc* it, uint32_t i, uint32_t u, uint32_t nmask,
-                                   uint32_t logN, R g) {
-  const uint32_t B = it->B, n = it->R + 1;
-  if (n <= 8u) return median_in_regs<8>(Y, it, i, u, nmask, logN, g, n);
-  if (n <= uint32_t(kRegRounds)) return median_in_regs<kRegRounds>(Y, it, i, u, nmask, logN, g, n);
+template <typename R, typename YV>
+__device__ cplx<R> median_estimate(YV yv, const IterDesc* it, uint32_t u, uint32_t nmask, uint32_t logN) {
+  const uint32_t n = it->R + 1;
+  if (n <= uint32_t(kRegRounds)) return median_in_regs<kRegRounds, R>(yv, it, u, nmask, logN, n);
   // more rounds than registers: order statistics by counting ranks
   const uint32_t lo = (n - 1) / 2, hi = n / 2;
   R lr = 0, hr = 0, li = 0, hi_ = 0;
   for (uint32_t a = 0; a < n; ++a) {
-    const cplx<R> ea = round_estimate(Y, B, i, a, it->T[a], u, nmask, logN, g);
+    const cplx<R> ea = round_estimate<R>(yv(a), it->T[a], u, nmask, logN);
     uint32_t ltr = 0, ler = 0, lti = 0, lei = 0;
     for (uint32_t b = 0; b < n; ++b) {
-      const cplx<R> eb = round_estimate(Y, B, i, b, it->T[b], u, nmask, logN, g);
+      const cplx<R> eb = round_estimate<R>(yv(b), it->T[b], u, nmask, logN);
       ltr += eb.re < ea.re;
       ler += eb.re <= ea.re;
       lti += eb.im < ea.im;
@@ -478,13 +564,12 @@ struct RealKey<double> {
   static __device__ __forceinline__ double value(T b) { return __longlong_as_double(int64_t(b)); }
 };
 
-// Top-K key: descending magnitude, ties to the smaller frequency.  The store
-// is sorted by frequency, so its index breaks ties the same way and names
-// the entry directly.
+// Top-K key: descending magnitude, ties to the smaller frequency; then the
+// selected keys again by ascending frequency.
 template <typename R>
 struct TopKey;
 template <>
-struct TopKey<float> {  // descending magnitude, then ascending frequency
+struct TopKey<float> {
   using T = uint64_t;
   static __device__ __forceinline__ T make(float mag2, uint32_t f) {
     return (uint64_t(~__float_as_uint(mag2)) << 32) | f;
@@ -492,7 +577,6 @@ struct TopKey<float> {  // descending magnitude, then ascending frequency
   static __device__ __forceinline__ T none() { return ~uint64_t(0); }
   static __device__ __forceinline__ uint32_t freq(T key) { return uint32_t(key); }
   static __device__ __forceinline__ T by_freq(uint32_t f) { return uint64_t(f); }
-  static __device__ __forceinline__ uint32_t freq_of_sorted(T key) { return uint32_t(key); }
 };
 template <>
 struct TopKey<double> {
@@ -503,7 +587,6 @@ struct TopKey<double> {
   static __device__ __forceinline__ T none() { return K128{~uint64_t(0), ~uint64_t(0)}; }
   static __device__ __forceinline__ uint32_t freq(T key) { return uint32_t(key.lo); }
   static __device__ __forceinline__ T by_freq(uint32_t f) { return K128{uint64_t(f), 0}; }
-  static __device__ __forceinline__ uint32_t freq_of_sorted(T key) { return uint32_t(key.hi); }
 };
 
 // Median of the real (IM = false) or imaginary parts of n loop estimates
@@ -526,411 +609,463 @@ __device__ R loop_median(const cplx<R>* vs, uint32_t n) {
   return (n & 1u) ? lo : (lo + hi) * R(0.5);
 }
 
+// Per-(candidate, round) pass: theta_j as a binary angle and the
+// round-to-round magnitude test of the detection rule.
+template <typename A, typename R>
+__device__ void angles_and_consistency(const cplx<R>* y0, const uint16_t* cand, const cplx<R>* rows, uint32_t ncand,
+                                       uint32_t R_, bool fp64, R rho, A* th, uint8_t* bad) {
+  const uint32_t nitems = R_ * ncand;
+  for (uint32_t q0 = 0; q0 < nitems; q0 += kBatch * kRecThreads) {
+    cplx<R> a[kBatch], b[kBatch];
+#pragma unroll
+    for (int e = 0; e < kBatch; ++e) {
+      const uint32_t q = q0 + uint32_t(e) * kRecThreads + threadIdx.x;
+      if (q < nitems) {
+        const uint32_t c = q % ncand;
+        a[e] = y0[cand[c]];
+        b[e] = rows[q];
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < kBatch; ++e) {
+      const uint32_t q = q0 + uint32_t(e) * kRecThreads + threadIdx.x;
+      if (q < nitems) {
+        th[q] = theta_bin<A>(a[e], b[e], fp64);
+        const R m0 = sqrt(a[e].re * a[e].re + a[e].im * a[e].im);
+        if (fabs(sqrt(b[e].re * b[e].re + b[e].im * b[e].im) - m0) > rho * m0) bad[q % ncand] = 1;
+      }
+    }
+  }
+}
+
+template <typename A, typename R>
+__device__ void locate_candidates(const PlanDesc* pd, const IterDesc* it, const R* ghat, const cplx<R>* y0,
+                                  const uint16_t* cand, const cplx<R>* rows, const A* th, const uint8_t* bad,
+                                  uint32_t ncand, uint32_t* cu, cplx<R>* cval) {
+  const uint32_t nmask = pd->N - 1, logN = pd->logN;
+  for (uint32_t c = threadIdx.x; c < ncand; c += kRecThreads) {
+    if (bad[c]) continue;
+    const uint32_t i = cand[c];
+    uint32_t dd = 0;
+    const uint32_t u = locate_bucket<A>(pd, it, i, [&](uint32_t j) { return th[(j - 1) * ncand + c]; }, &dd);
+    if (u == kNone) continue;
+    const R g = ghat[dd];
+    const cplx<R> yi = y0[i];
+    const cplx<R> med =
+        median_estimate<R>([&](uint32_t j) { return j == 0 ? yi : rows[(j - 1) * ncand + c]; }, it, u, nmask, logN);
+    if (g == R(0)) continue;
+    cval[c] = cplx<R>{med.re / g, med.im / g};
+    cu[i] = u;
+  }
+}
+
 template <typename R>
-__global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
+__global__ __launch_bounds__(kRecThreads, 2) void recover_kernel(SigArg arg) {
   __shared__ __attribute__((aligned(16))) unsigned char lds_buf[kLdsBytes];
-  __shared__ uint32_t hist[256];
+  __shared__ uint32_t hist[2 * 256];
   __shared__ uint32_t wsum[kWaves];
   __shared__ uint32_t sel[2];
   __shared__ uint32_t nrec_sh;
   __shared__ R sh_red[kWaves];
-  __shared__ uint64_t sh_u64[kWaves];
+  __shared__ typename RealKey<R>::T sh_key[kWaves];
   // the plan and the current iteration's descriptors, read in every phase
   __shared__ PlanDesc sh_pd;
   __shared__ IterDesc sh_it;
   using RK = RealKey<R>;
+  using KT = typename RK::T;
 
-  const uint32_t tid = threadIdx.x, NT = blockDim.x;
+  const uint32_t tid = threadIdx.x, NT = kRecThreads;
   const SignalDesc sd = load_signal(arg, blockIdx.x);
   copy_words(&sh_pd, sd.plan, sizeof(PlanDesc));
+  hist[tid] = 0;
+  hist[256 + tid] = 0;
+  if (tid == 0) nrec_sh = 0;
   __syncthreads();
   const PlanDesc* pd = &sh_pd;
   unsigned char* ws = reinterpret_cast<unsigned char*>(sd.ws);
   cplx<R>* Yall = reinterpret_cast<cplx<R>*>(sd.y);
   uint32_t* rf = reinterpret_cast<uint32_t*>(ws + pd->off_recf);
   cplx<R>* rv = reinterpret_cast<cplx<R>*>(ws + pd->off_recv);
-  uint32_t* hk = reinterpret_cast<uint32_t*>(ws + pd->off_htkey);
-  uint32_t* hi = reinterpret_cast<uint32_t*>(ws + pd->off_htidx);
-  uint32_t* g_cand_u = reinterpret_cast<uint32_t*>(ws + pd->off_candu);
-  uint32_t* g_cand_d = reinterpret_cast<uint32_t*>(ws + pd->off_candd);
-  cplx<R>* g_cand_v = reinterpret_cast<cplx<R>*>(ws + pd->off_candv);
-  uint64_t* gkeys = reinterpret_cast<uint64_t*>(ws + pd->off_keys);
-  R* g_p0 = reinterpret_cast<R*>(ws + pd->off_p0);
-  const uint32_t N = pd->N, nmask = N - 1, logN = pd->logN, logh = pd->log_hcap;
-  const uint32_t hmask = (1u << logh) - 1;
+  unsigned char* gwork = ws + pd->off_work;
+  const uint32_t N = pd->N, nmask = N - 1, logN = pd->logN;
   const bool vote = pd->combine == SFFT_COMBINE_VOTE;
+  const bool fp64 = pd->fp64_phase != 0;
+  // location in 32-bit binary angles when the block-centre phases are exact there
+  const bool ang32 = sizeof(R) == 4 && 1 + pd->logl + logN <= 32;
   uint32_t* nvote = reinterpret_cast<uint32_t*>(ws + pd->off_nvote);
   cplx<R>* votes = reinterpret_cast<cplx<R>*>(ws + pd->off_votes);
-
-  // empty store and hash index
-  for (uint32_t h = tid; h <= hmask; h += NT) hk[h] = kNone;
-  if (tid == 0) nrec_sh = 0;
-  __threadfence();
-  __syncthreads();
   uint32_t nrec = 0;
 
   for (uint32_t m = 0; m < pd->M; ++m) {
     copy_words(&sh_it, pd->iters + m, sizeof(IterDesc));
     __syncthreads();
     const IterDesc* it = &sh_it;
-    const uint32_t B = it->B, L = it->L, D = it->D, R1 = it->R + 1;
+    const uint32_t B = it->B, L = it->L, D = it->D, R_ = it->R;
     const R* ghat = reinterpret_cast<const R*>(pd->ghat) + it->ghat_off;
     const uint32_t sigma = it->sigma;
+    const cplx<R>* Yg = Yall + it->y_off;  // this iteration's (R+1) x B bucket block
+    const uint32_t nst = nrec;             // store entries when the iteration starts
+    const bool subtract = !vote && nst > 0;
+    const uint32_t nslot = it->reach + 1;  // buckets a coefficient can reach
+    Arena ar{lds_buf, gwork, 0u, 0ull};
 
-    // The vote (SFFT_COMBINE_VOTE) subtracts nothing: every loop sees the
-    // whole signal.
-    const uint32_t nsub = vote ? 0u : nrec;
-
-    // ---- LDS plan of the iteration ----
-    // The iteration's bucket block ((R+1) x B values) and the per-bucket
-    // arrays are staged in LDS when they fit beside the scratch that the
-    // subtraction and the detection need; otherwise they stay in the
-    // workspace.  The subtraction then updates the staged block in place and
-    // every later phase reads it from LDS.
+    // ---- 1. the store sorted by permuted frequency, and round 0 ----
+    // Cells of the top bits of u hold about one entry each; exact ranks
+    // inside a cell finish the sort, and the cell ends locate any u in O(1).
+    // The store and round 0 of the bucket values are read in one pass, and
+    // the window weights the subtraction needs are gathered while the cells
+    // are counted.
     uint32_t npow = 1, logc = 0;
-    while (npow < nsub) {
+    while (npow < nst) {
       npow <<= 1;
       ++logc;
     }
-    const uint32_t nslot = it->reach + 1;  // buckets a coefficient can reach
-    // subtraction scratch: cell ends, sorted keys, values (over the scattered
-    // keys), window weights per (entry, reachable bucket), one round's
-    // value x phase per entry, one round's sums per bucket
-    constexpr uint32_t CB = uint32_t(sizeof(cplx<R>));
-    const uint32_t o_sk = (npow * 4u + 15u) & ~15u;
-    const uint32_t o_sv = (o_sk + nsub * 8u + 15u) & ~15u;
-    const uint32_t o_gq = (o_sv + nsub * CB + 15u) & ~15u;
-    const uint32_t o_w = (o_gq + nsub * nslot * uint32_t(sizeof(R)) + 15u) & ~15u;
-    // then per bucket the bounds of its run, and (bucket values in the
-    // workspace) the sums of the rounds of one pass; rp rounds share a pass
-    auto sub_bytes = [&](uint32_t rp, bool staged) -> uint32_t {
-      if (nsub == 0) return 0u;
-      const uint32_t orun = (o_w + nsub * CB * rp + 15u) & ~15u;
-      return orun + B * 8u + (staged ? 0u : B * CB * rp);
-    };
-    const uint32_t det_need = B * uint32_t(sizeof(typename RK::T));
-    const uint32_t ys_bytes = (R1 * B * uint32_t(sizeof(cplx<R>)) + 15u) & ~15u;
-    const uint32_t pb_bytes = ((B * uint32_t(sizeof(R)) + 15u) & ~15u) + 2u * ((B * 4u + 15u) & ~15u) +
-                              B * uint32_t(sizeof(cplx<R>));
-    auto fits = [&](uint32_t rp, bool staged, bool pbs) -> bool {
-      const uint32_t sub = sub_bytes(rp, staged);
-      return (staged ? ys_bytes : 0u) + (pbs ? pb_bytes : 0u) + (sub > det_need ? sub : det_need) <=
-             uint32_t(kLdsBytes);
-    };
-    const bool y_lds = fits(1, true, false);
-    const bool pb_lds_plan = fits(1, y_lds, true);
-    uint32_t rp = 1;  // more rounds per pass only where the LDS plan above still holds
-    while (rp < uint32_t(kMaxRoundsPerPass) && fits(rp * 2, y_lds, pb_lds_plan)) rp *= 2;
-    const uint32_t o_run = (o_w + nsub * CB * rp + 15u) & ~15u;
-    const uint32_t o_ys = o_run + B * 8u;
-    const uint32_t sub_need = sub_bytes(rp, y_lds);
-    const uint32_t scr_need = sub_need > det_need ? sub_need : det_need;
-    const uint32_t pb_at = y_lds ? ys_bytes : 0u;
-    const bool pb_lds = pb_lds_plan;
-    const uint32_t scr_at = (pb_at + (pb_lds ? pb_bytes : 0u) + 15u) & ~15u;
-    unsigned char* scr = lds_buf + scr_at;
-    const uint32_t scr_bytes = uint32_t(kLdsBytes) - scr_at;
-    cplx<R>* const Yg = Yall + it->y_off;
-    cplx<R>* const Y = y_lds ? reinterpret_cast<cplx<R>*>(lds_buf) : Yg;
-    R* const p0 = pb_lds ? reinterpret_cast<R*>(lds_buf + pb_at) : g_p0;
-    uint32_t* const cand_u = pb_lds ? reinterpret_cast<uint32_t*>(lds_buf + pb_at + ((B * uint32_t(sizeof(R)) + 15u) & ~15u))
-                                    : g_cand_u;
-    uint32_t* const cand_d = pb_lds ? cand_u + ((B + 3u) & ~3u) : g_cand_d;
-    cplx<R>* const cand_v = pb_lds ? reinterpret_cast<cplx<R>*>(cand_d + ((B + 3u) & ~3u)) : g_cand_v;
-    typename RK::T* const ldskey = reinterpret_cast<typename RK::T*>(scr);
-    if (y_lds) {
-      for (uint32_t e = tid; e < R1 * B; e += NT) Y[e] = Yg[e];
-      __syncthreads();
+    const uint32_t cshift = logN - logc;  // npow <= rec_cap < N
+    uint32_t* cend = nullptr;
+    uint64_t* sk = nullptr;
+    cplx<R>* sv = nullptr;
+    if (nst > 0) {
+      cend = ar.take<uint32_t>(npow);
+      sk = ar.take<uint64_t>(nst);
+      sv = ar.take<cplx<R>>(nst);
     }
-
-    // ---- subtraction of the coefficients recovered so far ----
-    // Sorted by its permuted frequency u = sigma f mod N, the store lists the
-    // coefficients that leak into bucket i (circular distance |iL - u| <= D)
-    // as one circular run.  The sort is a counting sort on the top bits of u
-    // (about one entry per cell) followed by exact ranks inside each cell;
-    // the cell ends locate any run in O(1).  Then, round by round: every
-    // entry's value times its phase exp(-2 pi i T_j u / N) is formed once,
-    // evenly over the threads; a team of lanes per bucket adds window weight
-    // times that value over the bucket's run, closed by a fixed sequence of
-    // cross-lane adds; and the round's sums are taken off the bucket values
-    // in one pass.  The order of every sum depends only on the recovered set.
-    if (nsub > 0) {
-      const uint32_t cshift = logN - logc;  // npow <= rec_cap < N
-      const bool in_lds = sub_need <= scr_bytes;
-      unsigned char* base = in_lds ? scr : reinterpret_cast<unsigned char*>(gkeys);
-      uint32_t* cend = reinterpret_cast<uint32_t*>(base);  // cell counts, then cell ends
-      uint64_t* sk = reinterpret_cast<uint64_t*>(base + o_sk);
-      uint64_t* tmp = reinterpret_cast<uint64_t*>(base + o_sv);  // scattered keys, then values
-      cplx<R>* sv = reinterpret_cast<cplx<R>*>(base + o_sv);
-      R* gq = reinterpret_cast<R*>(base + o_gq);
-      cplx<R>* w = reinterpret_cast<cplx<R>*>(base + o_w);
-      RunBounds* run = reinterpret_cast<RunBounds*>(base + o_run);
-      cplx<R>* ysub = reinterpret_cast<cplx<R>*>(base + o_ys);
-      for (uint32_t c = tid; c < npow; c += NT) cend[c] = 0;
-      __syncthreads();
-      for (uint32_t k = tid; k < nsub; k += NT) atomicAdd(&cend[((sigma * rf[k]) & nmask) >> cshift], 1u);
+    cplx<R>* y0 = ar.take<cplx<R>>(B);
+    uint32_t* cu = ar.take<uint32_t>(B);  // located position per bucket, or kNone
+    R* gq = nullptr;                      // window weight per (sorted entry, reachable bucket)
+    RunBounds* run = nullptr;
+    cplx<R>* w0 = nullptr;                // v exp(-2 pi i T_0 u / N) per sorted entry
+    if (subtract) {
+      gq = ar.take<R>(uint64_t(nst) * nslot);
+      run = ar.take<RunBounds>(B);
+      w0 = ar.take<cplx<R>>(nst);
+    }
+    const Arena::Mark mk_det = ar.mark();
+    KT* pk = ar.take<KT>(B);  // |round 0|^2 as order-preserving keys (detection only)
+    const Arena::Mark mk_tmp = ar.mark();
+    uint32_t* raw_u = nst > 0 ? ar.take<uint32_t>(nst) : nullptr;
+    cplx<R>* raw_v = nst > 0 ? ar.take<cplx<R>>(nst) : nullptr;
+    uint64_t* tmp = nst > 0 ? ar.take<uint64_t>(nst) : nullptr;
+    R* graw = subtract ? ar.take<R>(uint64_t(nst) * nslot) : nullptr;  // weights by entry
+    for (uint32_t c = tid; c < npow && nst > 0; c += NT) cend[c] = 0;
+    {
+      const uint32_t nload = max(B, nst);
+      for (uint32_t i0 = 0; i0 < nload; i0 += kBatch * NT) {
+        cplx<R> y[kBatch], v[kBatch];
+        uint32_t f[kBatch];
+#pragma unroll
+        for (int e = 0; e < kBatch; ++e) {
+          const uint32_t i = i0 + uint32_t(e) * NT + tid;
+          if (i < B) y[e] = Yg[i];
+          if (i < nst) {
+            f[e] = rf[i];
+            v[e] = rv[i];
+          }
+        }
+#pragma unroll
+        for (int e = 0; e < kBatch; ++e) {
+          const uint32_t i = i0 + uint32_t(e) * NT + tid;
+          if (i < B) {
+            y0[i] = y[e];
+            cu[i] = kNone;
+            if (!subtract) pk[i] = RK::bits(y[e].re * y[e].re + y[e].im * y[e].im);
+          }
+          if (i < nst) {
+            raw_u[i] = (sigma * f[e]) & nmask;
+            raw_v[i] = v[e];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (nst > 0) {
+      for (uint32_t k = tid; k < nst; k += NT) atomicAdd(&cend[raw_u[k] >> cshift], 1u);
+      if (subtract) {
+        // window weight of each bucket an entry reaches (slot r: bucket
+        // i0(u) + r, i0 = ceil((u - D) / L)), as flat (entry, slot) items
+        const uint32_t ngq = nst * nslot;
+        for (uint32_t q0 = 0; q0 < ngq; q0 += kBatch * NT) {
+          R g[kBatch];
+#pragma unroll
+          for (int e = 0; e < kBatch; ++e) {
+            const uint32_t q = q0 + uint32_t(e) * NT + tid;
+            g[e] = R(0);
+            if (q < ngq) {
+              const uint32_t k = q / nslot, r = q - k * nslot;
+              const uint32_t u = raw_u[k];
+              const int64_t dist = (first_bucket(u, D, it->logL) + int64_t(r)) * int64_t(L) - int64_t(u);
+              const int64_t ad = dist < 0 ? -dist : dist;
+              if (ad <= int64_t(D)) g[e] = ghat[ad];
+            }
+          }
+#pragma unroll
+          for (int e = 0; e < kBatch; ++e) {
+            const uint32_t q = q0 + uint32_t(e) * NT + tid;
+            if (q < ngq) graw[q] = g[e];
+          }
+        }
+      }
       __syncthreads();
       block_scan_array(cend, npow, wsum);  // cend[c] = start of cell c
-      for (uint32_t k = tid; k < nsub; k += NT) {
-        const uint32_t u = (sigma * rf[k]) & nmask;
+      for (uint32_t k = tid; k < nst; k += NT) {
+        const uint32_t u = raw_u[k];
         tmp[atomicAdd(&cend[u >> cshift], 1u)] = (uint64_t(u) << 32) | k;  // cend[c] ends as the end of cell c
       }
       __syncthreads();
-      for (uint32_t p = tid; p < nsub; p += NT) {  // exact rank inside the cell
+      for (uint32_t p = tid; p < nst; p += NT) {  // exact rank inside the cell
         const uint64_t key = tmp[p];
         const uint32_t c = uint32_t(key >> 32) >> cshift;
         const uint32_t c0 = c ? cend[c - 1] : 0u, c1 = cend[c];
         uint32_t r = 0;
         for (uint32_t p2 = c0; p2 < c1; ++p2) r += tmp[p2] < key ? 1u : 0u;
-        sk[c0 + r] = key;
-      }
-      __syncthreads();
-      // number of sorted entries whose u is below x (x <= N)
-      auto lower = [&](uint32_t x) -> uint32_t {
-        if (x >= N) return nsub;
-        const uint32_t c = x >> cshift;
-        uint32_t q = c ? cend[c - 1] : 0u;
-        const uint32_t c1 = cend[c];
-        while (q < c1 && uint32_t(sk[q] >> 32) < x) ++q;
-        return q;
-      };
-      // values in sorted order and the window weight of each bucket an entry
-      // reaches (slot r: bucket i0(u) + r, i0 = ceil((u - D) / L)); a thread
-      // issues the loads of kVgBatch entries together
-      for (uint32_t qb = 0; qb < nsub; qb += kVgBatch * NT) {
-        uint64_t key[kVgBatch];
-        cplx<R> val[kVgBatch];
-#pragma unroll
-        for (int e = 0; e < kVgBatch; ++e) {
-          const uint32_t q = qb + uint32_t(e) * NT + tid;
-          key[e] = q < nsub ? sk[q] : 0;
-        }
-#pragma unroll
-        for (int e = 0; e < kVgBatch; ++e) {
-          const uint32_t q = qb + uint32_t(e) * NT + tid;
-          val[e] = q < nsub ? rv[uint32_t(key[e])] : cplx<R>{0, 0};
-        }
-#pragma unroll
-        for (int e = 0; e < kVgBatch; ++e) {
-          const uint32_t q = qb + uint32_t(e) * NT + tid;
-          if (q < nsub) {
-            const uint32_t u = uint32_t(key[e] >> 32);
-            const int64_t i0 = first_bucket(u, D, it->logL);
-            sv[q] = val[e];
-            for (uint32_t r = 0; r < nslot; ++r) {
-              const int64_t dist = (i0 + int64_t(r)) * int64_t(L) - int64_t(u);
-              const int64_t ad = dist < 0 ? -dist : dist;
-              gq[q * nslot + r] = ad <= int64_t(D) ? ghat[ad] : R(0);
-            }
-          }
+        const uint32_t q = c0 + r, k = uint32_t(key);
+        sk[q] = key;
+        const cplx<R> v = raw_v[k];
+        sv[q] = v;
+        if (subtract) {
+          for (uint32_t s2 = 0; s2 < nslot; ++s2) gq[q * nslot + s2] = graw[k * nslot + s2];
+          // round 0's value x phase, once per entry
+          w0[q] = cmul(v, expi<R>((it->T[0] * uint32_t(key >> 32)) & nmask, logN, R(-1)));
         }
       }
       __syncthreads();
+    }
+    ar.release(mk_tmp);
+    // number of sorted entries whose u is below x (x <= N)
+    auto lower = [&](uint32_t x) -> uint32_t {
+      if (x >= N) return nst;
+      const uint32_t c = x >> cshift;
+      uint32_t q = c ? cend[c - 1] : 0u;
+      const uint32_t c1 = cend[c];
+      while (q < c1 && uint32_t(sk[q] >> 32) < x) ++q;
+      return q;
+    };
+
+    // ---- 2. round 0 of every bucket, minus the store's contributions ----
+    uint32_t S = 1;  // lanes per bucket in the run sums
+    if (subtract) {
       // every bucket's run: its first entry and its length (the same in every round)
       const uint32_t span = 2 * D + 1;  // < N
       for (uint32_t i = tid; i < B; i += NT) {
         const uint32_t a = (i * L - D) & nmask;  // first u of the run
         const uint64_t stop = uint64_t(a) + span;
         const uint32_t q0 = lower(a);
-        const uint32_t cnt = stop <= N ? lower(uint32_t(stop)) - q0 : nsub - q0 + lower(uint32_t(stop - N));
+        const uint32_t cnt = stop <= N ? lower(uint32_t(stop)) - q0 : nst - q0 + lower(uint32_t(stop - N));
         run[i] = RunBounds{q0, cnt};
       }
       __syncthreads();
       // team size: enough lanes to cover the mean run, as many as let one
-      // pass take all buckets (at least 1, at most 64)
-      const double mean_run = double(nsub) * double(2 * D + 1) / double(N);
-      uint32_t S = 1;
-      while (S < 64 && double(S) < mean_run && S * 2u * B <= NT) S <<= 1;
-      const uint32_t team = tid / S, lane = tid & (S - 1), nteams = NT / S;
-      for (uint32_t j0 = 0; j0 < R1; j0 += rp) {
-        const uint32_t nj = min(rp, R1 - j0);
-        for (uint32_t q = tid; q < nsub; q += NT) {
-          const uint32_t u = uint32_t(sk[q] >> 32);
-          const cplx<R> v = sv[q];
-          for (uint32_t r = 0; r < nj; ++r)
-            w[q * rp + r] = cmul(v, expi<R>((it->T[j0 + r] * u) & nmask, logN, R(-1)));
-        }
-        __syncthreads();
-        for (uint32_t base_i = 0; base_i < B; base_i += nteams) {  // uniform trip count per wave
-          const uint32_t i = base_i + team;
-          cplx<R> acc[kMaxRoundsPerPass];
-#pragma unroll
-          for (int r = 0; r < kMaxRoundsPerPass; ++r) acc[r] = cplx<R>{0, 0};
-          if (i < B) {
-            const RunBounds rb = run[i];
-            const uint32_t q0 = rb.first, cnt = rb.count;
-            for (uint32_t v = lane; v < cnt; v += S) {
-              uint32_t q = q0 + v;
-              q = q >= nsub ? q - nsub : q;
-              const uint32_t u = uint32_t(sk[q] >> 32);
-              const uint32_t slot = (i - uint32_t(first_bucket(u, D, it->logL))) & (B - 1);
-              const R g = gq[q * nslot + slot];
-#pragma unroll
-              for (int r = 0; r < kMaxRoundsPerPass; ++r)
-                if (uint32_t(r) < nj) acc[r] = cadd(acc[r], cscale(w[q * rp + uint32_t(r)], g));
-            }
-          }
-#pragma unroll
-          for (int r = 0; r < kMaxRoundsPerPass; ++r) {
-            if (uint32_t(r) < nj) {  // uniform; the team's sums land in its last lane
-              acc[r].re = team_sum(acc[r].re, S);
-              acc[r].im = team_sum(acc[r].im, S);
-            }
-          }
-          if (i < B && lane == S - 1) {
-#pragma unroll
-            for (int r = 0; r < kMaxRoundsPerPass; ++r) {
-              if (uint32_t(r) < nj) {
-                cplx<R>* yp = Y + size_t(j0 + uint32_t(r)) * B + i;
-                if (y_lds) *yp = csub(*yp, acc[r]);  // staged block: in place
-                else ysub[size_t(r) * B + i] = acc[r];
-              }
-            }
-          }
-        }
-        __syncthreads();
-        if (y_lds) continue;
-        // bucket values in the workspace: take the pass's sums off, loads batched
-        for (uint32_t r = 0; r < nj; ++r) {
-          cplx<R>* Yj = Y + size_t(j0 + r) * B;
-          const cplx<R>* sj = ysub + size_t(r) * B;
-          for (uint32_t ib = 0; ib < B; ib += kVgBatch * NT) {
-            cplx<R> yv[kVgBatch];
-#pragma unroll
-            for (int e = 0; e < kVgBatch; ++e) {
-              const uint32_t i = ib + uint32_t(e) * NT + tid;
-              if (i < B) yv[e] = Yj[i];
-            }
-#pragma unroll
-            for (int e = 0; e < kVgBatch; ++e) {
-              const uint32_t i = ib + uint32_t(e) * NT + tid;
-              if (i < B) Yj[i] = csub(yv[e], sj[i]);
-            }
-          }
-        }
-        __syncthreads();
+      // pass take all buckets (S B <= NT; at least 1, at most 64)
+      const double mean_run = double(nst) * double(2 * D + 1) / double(N);
+      while (S < 64 && double(S) < mean_run && S * 2u * B <= 2u * NT) S <<= 1;
+    }
+    // The sum over bucket i's run of Ghat x v exp(-2 pi i T_j u / N), by the
+    // S lanes of a team: lane-strided partial sums closed by a fixed butterfly.
+    // wq, when given, holds v exp(-2 pi i T_j u / N) per sorted entry.
+    auto run_sum = [&](uint32_t i, uint32_t Tj, const cplx<R>* wq, uint32_t lane, uint32_t S_) -> cplx<R> {
+      cplx<R> acc{0, 0};
+      const RunBounds rb = run[i];
+      for (uint32_t v = lane; v < rb.count; v += S_) {
+        uint32_t q = rb.first + v;
+        q = q >= nst ? q - nst : q;
+        const uint32_t u = uint32_t(sk[q] >> 32);
+        const uint32_t slot = (i - uint32_t(first_bucket(u, D, it->logL))) & (B - 1);
+        const R g = gq[q * nslot + slot];
+        const cplx<R> w = wq ? wq[q] : cmul(sv[q], expi<R>((Tj * u) & nmask, logN, R(-1)));
+        acc = cadd(acc, cscale(w, g));
       }
+      return acc;
+    };
+    if (subtract) {
+      const uint32_t team = tid / S, lane = tid & (S - 1), nteams = NT / S;
+      for (uint32_t base_i = 0; base_i < B; base_i += nteams) {  // uniform trip count per wave
+        const uint32_t i = base_i + team;
+        cplx<R> acc = i < B ? run_sum(i, it->T[0], w0, lane, S) : cplx<R>{0, 0};
+        acc.re = team_sum(acc.re, S);
+        acc.im = team_sum(acc.im, S);
+        if (i < B && lane == S - 1) {
+          const cplx<R> v = csub(y0[i], acc);
+          y0[i] = v;
+          pk[i] = RK::bits(v.re * v.re + v.im * v.im);
+        }
+      }
+      __syncthreads();
     }
 
-    // ---- singleton detection ----
-    R mx = 0;
-    for (uint32_t i = tid; i < B; i += NT) {
-      const cplx<R> y0 = Y[i];
-      const R p = y0.re * y0.re + y0.im * y0.im;
-      p0[i] = p;
-      ldskey[i] = RK::bits(p);
-      mx = p > mx ? p : mx;
-      const R m0 = sqrt(p);
-      uint32_t cons = 1;
-      for (uint32_t j = 1; j < R1; ++j) {
-        const cplx<R> yj = Y[size_t(j) * B + i];
-        if (fabs(sqrt(yj.re * yj.re + yj.im * yj.im) - m0) > R(pd->rho) * m0) cons = 0;
+    // ---- 3. detection threshold from round 0 ----
+    // The median of the B powers (the two middle order statistics) and the
+    // largest: by counting ranks for a few buckets, else by radix selection.
+    KT ka, kb, kmax;
+    if (B <= 128) {  // B is a power of two >= 16
+      if (tid < B) {
+        const KT k = pk[tid];
+        uint32_t lt = 0, le = 0;
+        for (uint32_t b0 = 0; b0 < B; b0 += 16) {
+          KT o[16];
+#pragma unroll
+          for (int r = 0; r < 16; ++r) o[r] = pk[b0 + uint32_t(r)];
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            lt += o[r] < k ? 1u : 0u;
+            le += o[r] <= k ? 1u : 0u;
+          }
+        }
+        const uint32_t r = B / 2 - 1;
+        if (lt <= r && r < le) sh_key[0] = k;
+        if (lt <= r + 1 && r + 1 < le) sh_key[1] = k;
+        if (le == B) sh_key[2] = k;
       }
-      cand_u[i] = cons;
+      __syncthreads();
+      ka = sh_key[0];
+      kb = sh_key[1];
+      kmax = sh_key[2];
+    } else {
+      KT mk = 0;
+      for (uint32_t i = tid; i < B; i += NT) mk = pk[i] > mk ? pk[i] : mk;
+      kmax = block_max(mk, sh_key);
+      block_select2(pk, B, B / 2 - 1, hist, sel, wsum, sh_key, &ka, &kb);
     }
-    mx = block_max(mx, sh_red);
-    // median of the B powers: the two middle order statistics
-    const typename RK::T ka = block_select(ldskey, B, B / 2 - 1, hist, wsum, sel);
-    uint32_t le = 0;
-    typename RK::T above = ~typename RK::T(0);
-    for (uint32_t i = tid; i < B; i += NT) {
-      const typename RK::T kk = ldskey[i];
-      le += kk <= ka ? 1u : 0u;
-      if (kk > ka && kk < above) above = kk;
-    }
-    le = block_sum(le, wsum);
-    const typename RK::T kb = le >= B / 2 + 1 ? ka : block_min(above, reinterpret_cast<typename RK::T*>(sh_u64));
+    const R mx = RK::value(kmax);
     const R med = (RK::value(ka) + RK::value(kb)) * R(0.5);
     const R thr_noise = R(2.0 * it->log_B) * (med / R(0.69314718055994530942));
     const R thr_floor = R(pd->eta * pd->eta) * mx;
     const R thr = thr_noise > thr_floor ? thr_noise : thr_floor;
+    __syncthreads();  // sh_key is read before it is written again
+    ar.release(mk_det);
 
-    // ---- location, verification, median estimation ----
-    // The buckets that pass the screen are listed first (in bucket order, a
-    // contiguous chunk per thread), so that the long location chains run on
-    // full wavefronts instead of on the few lanes whose bucket is active.
-    uint32_t* act = reinterpret_cast<uint32_t*>(scr);  // the median keys are no longer needed
-    uint32_t nact;
+    // ---- 4. candidate buckets (above the threshold), in bucket order ----
+    uint32_t ncand;
+    uint16_t* cand;  // bucket indices (B <= 16384)
     {
       const uint32_t chunk = (B + NT - 1) / NT;
       const uint32_t lo = min(B, tid * chunk), hi = min(B, lo + chunk);
       uint32_t mine = 0;
       for (uint32_t i = lo; i < hi; ++i) {
-        const R p = p0[i];
-        mine += (cand_u[i] && p >= thr && p > R(0)) ? 1u : 0u;
+        const cplx<R> v = y0[i];
+        const R p = v.re * v.re + v.im * v.im;
+        mine += (p >= thr && p > R(0)) ? 1u : 0u;
       }
-      uint32_t at = block_excl_scan(mine, wsum, &nact);
+      uint32_t at = block_excl_scan(mine, wsum, &ncand);
+      cand = ar.take<uint16_t>(ncand);
       for (uint32_t i = lo; i < hi; ++i) {
-        const R p = p0[i];
-        if (cand_u[i] && p >= thr && p > R(0)) act[at++] = i;
+        const cplx<R> v = y0[i];
+        const R p = v.re * v.re + v.im * v.im;
+        if (p >= thr && p > R(0)) cand[at++] = uint16_t(i);
       }
-      __syncthreads();
-      for (uint32_t i = lo; i < hi; ++i) cand_u[i] = kNone;
-      __syncthreads();
     }
-    for (uint32_t a = tid; a < nact; a += NT) {
-      const uint32_t i = act[a];
-      uint32_t dd = 0;
-      const uint32_t u = locate_bucket<R>(pd, it, Y, i, &dd);
-      const R g = u != kNone ? ghat[dd] : R(0);
-      if (u != kNone && g != R(0)) {
-        cand_v[i] = median_estimate<R>(Y, it, i, u, nmask, logN, g);
-        cand_d[i] = dd;
-        cand_u[i] = u;
+    uint8_t* bad = ar.take<uint8_t>(ncand);  // failed the round-to-round test
+    cplx<R>* rows = ar.take<cplx<R>>(uint64_t(R_) * ncand);  // round j of candidate c at (j-1) ncand + c
+    for (uint32_t c = tid; c < ncand; c += NT) bad[c] = 0;
+    __syncthreads();
+
+    // ---- 5. rounds 1..R of the candidates, minus the store's contributions ----
+    const uint32_t nitems = R_ * ncand;
+    if (!subtract) {
+      for (uint32_t q0 = 0; q0 < nitems; q0 += kBatchY * NT) {
+        cplx<R> v[kBatchY];
+#pragma unroll
+        for (int e = 0; e < kBatchY; ++e) {
+          const uint32_t q = q0 + uint32_t(e) * NT + tid;
+          if (q < nitems) {
+            const uint32_t j = 1 + q / ncand, c = q - (j - 1) * ncand;
+            v[e] = Yg[size_t(j) * B + cand[c]];
+          }
+        }
+#pragma unroll
+        for (int e = 0; e < kBatchY; ++e) {
+          const uint32_t q = q0 + uint32_t(e) * NT + tid;
+          if (q < nitems) rows[q] = v[e];
+        }
+      }
+    } else {
+      const double mean_run = double(nst) * double(2 * D + 1) / double(N);
+      uint32_t S2 = 1;
+      while (S2 < 64 && double(S2) < mean_run && S2 * 2u * nitems <= NT) S2 <<= 1;
+      const uint32_t team = tid / S2, lane = tid & (S2 - 1), nteams = NT / S2;
+      for (uint32_t base_q = 0; base_q < nitems; base_q += nteams) {  // uniform trip count per wave
+        const uint32_t q = base_q + team;
+        cplx<R> acc{0, 0};
+        uint32_t j = 1, i = 0;
+        if (q < nitems) {
+          j = 1 + q / ncand;
+          i = cand[q - (j - 1) * ncand];
+          acc = run_sum(i, it->T[j], nullptr, lane, S2);
+        }
+        acc.re = team_sum(acc.re, S2);
+        acc.im = team_sum(acc.im, S2);
+        if (q < nitems && lane == S2 - 1) rows[q] = csub(Yg[size_t(j) * B + i], acc);
       }
     }
     __syncthreads();
 
-    // ---- dedupe (nearest bucket centre wins) and rec[f] += v ----
-    for (uint32_t i = tid; i < B; i += NT) {
-      const uint32_t u = cand_u[i];
+    // ---- 6. phase differences and the round-to-round test ----
+    // ---- 7. location, verification, median estimation ----
+    cplx<R>* cval;  // estimates of the located candidates
+    if (ang32) {
+      uint32_t* th = ar.take<uint32_t>(nitems);
+      cval = ar.take<cplx<R>>(ncand);
+      angles_and_consistency<uint32_t, R>(y0, cand, rows, ncand, R_, fp64, R(pd->rho), th, bad);
+      __syncthreads();
+      locate_candidates<uint32_t, R>(pd, it, ghat, y0, cand, rows, th, bad, ncand, cu, cval);
+    } else {
+      uint64_t* th = ar.take<uint64_t>(nitems);
+      cval = ar.take<cplx<R>>(ncand);
+      angles_and_consistency<uint64_t, R>(y0, cand, rows, ncand, R_, fp64, R(pd->rho), th, bad);
+      __syncthreads();
+      locate_candidates<uint64_t, R>(pd, it, ghat, y0, cand, rows, th, bad, ncand, cu, cval);
+    }
+    __syncthreads();
+
+    // ---- 8. dedupe (nearest bucket centre wins) and rec[f] += v ----
+    for (uint32_t c = tid; c < ncand; c += NT) {
+      const uint32_t i = cand[c];
+      const uint32_t u = cu[i];
       if (u == kNone) continue;
-      const uint32_t d = cand_d[i];
+      const uint32_t d1 = (i * L - u) & nmask;
+      const uint32_t d = min(d1, N - d1);
       bool keep = true;
       for (uint32_t dd = 1; dd <= it->reach; ++dd) {
-        const uint32_t i1 = (i - dd) & (B - 1), i2 = (i + dd) & (B - 1);
-        if (i1 != i && cand_u[i1] == u && (cand_d[i1] < d || (cand_d[i1] == d && i1 < i))) keep = false;
-        if (i2 != i && cand_u[i2] == u && (cand_d[i2] < d || (cand_d[i2] == d && i2 < i))) keep = false;
+        const uint32_t nb[2] = {(i - dd) & (B - 1), (i + dd) & (B - 1)};
+        for (int s = 0; s < 2; ++s) {
+          const uint32_t i2 = nb[s];
+          if (i2 == i || cu[i2] != u) continue;
+          const uint32_t e1 = (i2 * L - u) & nmask;
+          const uint32_t d2 = min(e1, N - e1);
+          if (d2 < d || (d2 == d && i2 < i)) keep = false;
+        }
       }
       if (!keep) continue;
       const uint32_t f = (it->sigma_inv * u) & nmask;
-      const cplx<R> v = cand_v[i];
-      uint32_t h = hslot(f, logh);
-      for (uint32_t probe = 0; probe <= hmask; ++probe) {
-        const uint32_t k = hkey(hk, h);
-        if (k == f) {  // seen in an earlier iteration
-          const uint32_t e = hi[h];
-          if (vote) {  // one estimate per loop (f is unique within a loop): at most M per entry
-            const uint32_t c = nvote[e];
-            if (c < pd->M) {
-              votes[size_t(e) * pd->M + c] = v;
-              nvote[e] = c + 1;
-            }
-          } else {
-            rv[e] = cadd(rv[e], v);
+      const cplx<R> v = cval[c];
+      // is f in the store?  The store sorted by u under this iteration's sigma
+      // holds it at the position of u, if anywhere.
+      uint32_t q = kNone;
+      if (nst > 0) {
+        const uint32_t p = lower(u);
+        if (p < nst && uint32_t(sk[p] >> 32) == u) q = p;
+      }
+      if (q != kNone) {
+        const uint32_t e = uint32_t(sk[q]);
+        if (vote) {  // one estimate per loop (f is unique within a loop): at most M per entry
+          const uint32_t cn = nvote[e];
+          if (cn < pd->M) {
+            votes[size_t(e) * pd->M + cn] = v;
+            nvote[e] = cn + 1;
           }
-          break;
+        } else {
+          rv[e] = cadd(sv[q], v);
         }
-        if (k == kNone) {
-          const uint32_t prev = atomicCAS(hk + h, kNone, f);
-          if (prev == kNone) {
-            const uint32_t e = atomicAdd(&nrec_sh, 1u);
-            rf[e] = f;
-            rv[e] = v;
-            if (vote) {
-              nvote[e] = 1;
-              votes[size_t(e) * pd->M] = v;
-            }
-            hi[h] = e;
-            break;
-          }
+      } else {
+        const uint32_t e = atomicAdd(&nrec_sh, 1u);
+        rf[e] = f;
+        rv[e] = v;
+        if (vote) {
+          nvote[e] = 1;
+          votes[size_t(e) * pd->M] = v;
         }
-        h = (h + 1) & hmask;
       }
     }
     __syncthreads();
     nrec = nrec_sh;
-    __syncthreads();
   }
 
   // ---- the vote over loops: keep f when at least half of the loops located it ----
@@ -947,8 +1082,9 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
   using TK = TopKey<R>;
   uint32_t npow = 1;
   while (npow < nrec) npow <<= 1;
-  const bool in_lds = npow * sizeof(typename TK::T) <= uint32_t(kLdsBytes);
-  typename TK::T* tk = in_lds ? reinterpret_cast<typename TK::T*>(lds_buf) : reinterpret_cast<typename TK::T*>(gkeys);
+  Arena ar{lds_buf, gwork, 0u, 0ull};
+  typename TK::T* tk = ar.take<typename TK::T>(npow);
+  uint32_t* tp = ar.take<uint32_t>(npow);  // store entry of each key
   uint32_t nz = 0;
   for (uint32_t k = tid; k < npow; k += NT) {
     if (k < nrec) {
@@ -959,11 +1095,12 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
     } else {
       tk[k] = TK::none();
     }
+    tp[k] = k;
   }
   nz = block_sum(nz, wsum);
-  if (npow > 1) block_bitonic_sort(tk, npow);
+  if (npow > 1) block_bitonic_sort(tk, tp, npow);
   const uint32_t Kp = min(pd->K, nz);
-  // the selected frequencies, sorted ascending
+  // the selected frequencies, sorted ascending (payloads follow their keys)
   uint32_t kpow = 1;
   while (kpow < Kp) kpow <<= 1;
   for (uint32_t c = tid; c < kpow; c += NT) {  // each thread rewrites only its own slots
@@ -971,13 +1108,12 @@ __global__ __launch_bounds__(kRecThreads) void recover_kernel(SigArg arg) {
     tk[c] = key;
   }
   __syncthreads();
-  if (kpow > 1) block_bitonic_sort(tk, kpow);
+  if (kpow > 1) block_bitonic_sort(tk, tp, kpow);
   cplx<R>* outv = reinterpret_cast<cplx<R>*>(sd.val);
   for (uint32_t c = tid; c < Kp; c += NT) {
-    const uint32_t f = TK::freq_of_sorted(tk[c]);
-    const uint32_t e = ht_find(hk, hi, f, logh);
-    sd.idx[c] = int64_t(f);
-    outv[c] = e != kNone ? rv[e] : cplx<R>{0, 0};
+    const uint32_t e = tp[c];
+    sd.idx[c] = int64_t(rf[e]);
+    outv[c] = rv[e];
   }
   if (tid == 0) *sd.count = int64_t(Kp);
 }
