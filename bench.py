@@ -583,6 +583,65 @@ def main():
                  "recall_first_8": round(float(np.mean(rec)), 4),
                  "note": "a coefficient that collides in more than half of the loops is dropped"}, ov)
 
+    def plain_form(reps):
+        """One signal of the metric workload (signal 0, the same plan), as a
+        caller with a single signal runs it: sfft_execute (fold, bucket DFT and
+        recovery launched on the stream), and the same three stages replayed
+        from a graph (a batch of one)."""
+        x0 = X[0].contiguous() if dt != "f16x2" else X[0].contiguous().view(torch.float16)
+        sc0 = scales[0]
+        outs = plan.execute(x0, sc0)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for _ in range(3):
+            plan.execute(x0, sc0)
+        e0.record(stream)
+        for _ in range(reps):
+            sfft.sfft_execute(plan.handle, x0, sc0, outs[0], outs[1], outs[2])
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_exec = e0.elapsed_time(e1) / reps
+        b1 = sfft.Batch([plan])
+        o1 = b1.outputs(dev)
+        for _ in range(3):
+            b1.execute([x0], scales=[sc0], outs=o1)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            b1.execute([x0], scales=[sc0], outs=o1)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_graph = e0.elapsed_time(e1) / reps
+        b1.close()
+        log(f"[plain single signal] execute {ms_exec:.4f} ms, graph {ms_graph:.4f} ms")
+        return {"signals": 1, "layout": "one buffer", "reps": reps,
+                "execute_ms": round(ms_exec, 4), "execute_signals_per_s": round(1e3 / ms_exec, 1),
+                "graph_ms": round(ms_graph, 4), "graph_signals_per_s": round(1e3 / ms_graph, 1),
+                "note": "one signal keeps one workgroup busy through the twelve dependent iterations of "
+                        "the recovery; the rest of the GPU idles"}
+
+    def independent_plans_form(steps):
+        """The metric batch with one plan per signal (plan seeds 602 + i, so
+        every signal has its own draws of sigma and tau), one buffer per
+        signal: the layout a batch of independently planned signals needs."""
+        from concurrent.futures import ThreadPoolExecutor
+
+        t1 = time.perf_counter()
+        with ThreadPoolExecutor(max_workers=16) as ex:
+            plans_i = list(ex.map(lambda i: sfft.Plan(N, K, B, w, M, l, q, delta=delta, seed=plan_seed + i,
+                                                      dtype=dt), range(n)))
+        log(f"[independent plans] {n} plans built in {time.perf_counter() - t1:.1f}s")
+        bi = sfft.Batch(plans_i)
+        oi_ = bi.outputs(dev)
+        xs = [X[i] for i in range(n)]
+        r = time_batch(bi, lambda: bi.execute(xs, scales=scales, outs=oi_), steps, "independent plans", False)
+        bi.close()
+        return {"plans": f"one per signal, seeds {plan_seed}..{plan_seed + n - 1}", "layout": "per-signal",
+                "signals_per_s": round(r["value"], 1), "ms_per_step": round(r["ms_per_step"], 4),
+                "stage_ms": {"fold": round(r["stage_ms"][0], 4), "bucket_fft": round(r["stage_ms"][1], 4),
+                             "recover": round(r["stage_ms"][2], 4)},
+                "graph_ms_per_step": round(r["graph_ms_per_step"], 4), "fold_launch": r["fold_cfg"]}, (plans_i, oi_)
+
     main_res = run_layout(args.layout, args.steps)
     context = None
     if not args.no_context:
@@ -600,6 +659,9 @@ def main():
     if not args.no_forms and dt == "c64":
         forms["direct_location"] = direct_form(max(2, args.steps // 2))
         forms["vote"], form_outs["vote"] = vote_form(max(2, args.steps // 2))
+    if not args.no_forms:
+        forms["plain"] = plain_form(20)
+        forms["independent_plans"], form_outs["independent_plans"] = independent_plans_form(max(2, args.steps // 2))
     if args.large_form:
         forms["large_precision"] = large_form(args.large_form, max(2, args.steps // 2))
 
@@ -659,7 +721,7 @@ def main():
         P = O.make_plan(N, K, B, w, M, l, Fraction(q), delta, seed=plan_seed)
         idxs, vals, counts = outs
         cnt = counts.cpu().numpy()
-        spent, done, same, worst = 0.0, 0, 0, 0.0
+        spent, done, same, worst, worst_pc, pcs = 0.0, 0, 0, 0.0, 0.0, []
         host = host_cpu()
         while done < n and (spent < args.cpu_seconds or done == 0):
             xh = host_copy(torch, X, done, dt, scales[done])
@@ -673,13 +735,19 @@ def main():
             if np.array_equal(gi, oi):
                 same += 1
                 worst = max(worst, float(np.linalg.norm(gv - ov) / max(np.linalg.norm(ov), 1e-300)))
+                pc = np.abs(gv - ov) / np.maximum(np.abs(ov), 1e-300)
+                worst_pc = max(worst_pc, float(pc.max()) if len(pc) else 0.0)
+                pcs.append(pc)
             done += 1
         cpu = {"value": round(done / spent, 4), "unit": "signals/s", "cores": 1, "kind": "oracle",
                "sample": f"first {done} signals of the batch (same inputs), FP64 NumPy oracle, plan untimed",
                "threads": "one: BLAS/OpenMP pools limited to 1 thread while timed (threadpoolctl); "
                           "NumPy's FFT, sort and bincount are single-threaded",
                "thread_pools_during_timing": pools, "host_cpu": host}
-        parity = {"signals_checked": done, "support_identical": same, "max_rel_l2_identical": worst}
+        allpc = np.concatenate(pcs) if pcs else np.zeros(1)
+        parity = {"signals_checked": done, "support_identical": same, "max_rel_l2_identical": worst,
+                  "per_coefficient_rel_err": {"max": worst_pc, "p99": float(np.quantile(allpc, 0.99)),
+                                              "median": float(np.median(allpc)), "coefficients": int(allpc.size)}}
         log(f"oracle: {done} signals in {spent:.1f}s; parity {same}/{done}, max rel-L2 {worst:.2e}")
         # the other forms, a few signals each (not timed)
         if "precision" in form_outs:
@@ -714,6 +782,23 @@ def main():
             forms["batching"]["parity"] = {"signals_checked": len(agree), "min_support_agreement": round(min(agree), 4),
                                            "max_rel_l2_common": worst_b,
                                            "note": "noisy inputs: decisions near the threshold may flip"}
+
+        if "independent_plans" in form_outs:
+            plans_i, (ii, vi, ci) = form_outs["independent_plans"]
+            chk, samei, worsti, worsti_pc = 0, 0, 0.0, 0.0
+            for s_ in (0, n - 1):
+                Pi = O.make_plan(N, K, B, w, M, l, Fraction(q), delta, seed=plan_seed + s_)
+                oi, ov_, _ = O.sfft(host_copy(torch, X, s_, dt, scales[s_]), Pi)
+                c = int(ci[s_].item())
+                gi, gv = ii[s_][:c].cpu().numpy(), vi[s_][:c].cpu().numpy().astype(np.complex128)
+                chk += 1
+                if np.array_equal(gi, oi):
+                    samei += 1
+                    worsti = max(worsti, float(np.linalg.norm(gv - ov_) / max(np.linalg.norm(ov_), 1e-300)))
+                    worsti_pc = max(worsti_pc, float(np.max(np.abs(gv - ov_) / np.maximum(np.abs(ov_), 1e-300))))
+            forms["independent_plans"]["parity"] = {"signals_checked": chk, "support_identical": samei,
+                                                    "max_rel_l2_identical": worsti,
+                                                    "max_per_coefficient_rel_err": worsti_pc}
 
         if "vote" in form_outs:
             iv, vv, cv = form_outs["vote"]
