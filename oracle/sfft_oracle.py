@@ -23,8 +23,9 @@ in the design notes):
   * Location (Sec. 3.2): extended first region L + 2e (e = window transition
     half-width), integer schedule tau_j = floor(N / len_j), rational block
     centres, floor for the region start, a final enumeration step.
-  * Detection, verification and dedupe rules are readings of their own (the paper
-    assumes isolated buckets).
+  * Detection and verification rules are readings of their own (the paper
+    assumes isolated buckets).  Verification accepts a located position only
+    in its home bucket, the one whose range Lemma 1 and Eq. 14 assign it.
   * Estimation takes the median over the R+1 rounds of one iteration.
   * The two-round location of sFFT3.0, which the paper sets against sFFT4.0
     (Sec. 1, Sec. 3.1: R_m = 2 rounds), is read as offsets tau0 and tau0 + 1
@@ -52,7 +53,7 @@ __all__ = [
     "location_schedule", "hash_to_bins", "subtract", "detect", "locate",
     "verify", "estimate", "sfft", "circ_dist", "samples_per_signal",
     "window_spectrum", "bucket_range", "phases", "multiscale_upper_bound",
-    "extension_lower_bound", "BLK", "ENUM", "DIRECT", "combine_votes", "reconstruct",
+    "extension_lower_bound", "BLK", "ENUM", "DIRECT", "combine_votes", "reconstruct", "home_bucket",
 ]
 
 TWO_PI = 2.0 * math.pi
@@ -364,13 +365,19 @@ def locate(theta: list, i: int, it: Iteration, N: int, l: int, q: Fraction) -> i
     raise AssertionError("schedule must end with an enumeration step")
 
 
+def home_bucket(u: int, L: int, B: int) -> int:
+    """The bucket that holds position u: the i with u in [iL - L/2, iL + L/2)
+    (the bucket range of Lemma 1 and Eq. 14, halves rounded up)."""
+    return ((u + L // 2) // L) % B
+
+
 def verify(theta: list, u: int, i: int, it: Iteration, N: int, l: int) -> bool:
-    """Accept u only if every round's phase agrees with it to within pi/l
-    (the Eq. 18 bound on the phase error) and u lies within the reach
-    L/2 + e of the bucket centre (where Ghat is tabulated)."""
-    dist = abs(i * it.L - u)
-    dist = min(dist, N - dist)
-    if dist > it.D:
+    """Accept u only if bucket i is its home bucket (Eq. 14 estimates a
+    coefficient from the bucket whose range [iL - L/2, iL + L/2) holds it;
+    the location searched a wider region, L + 2e, so that leakage from the
+    transition band cannot alias) and every round's phase agrees with it to
+    within pi/l (the Eq. 18 bound on the phase error)."""
+    if home_bucket(u, it.L, it.B) != i:
         return False
     for j in range(1, it.R + 1):
         if circ_dist(theta[j], TWO_PI * ((it.taus[j] * u) % N) / N) > math.pi / l:
@@ -407,17 +414,14 @@ def combine_votes(votes: dict, loops: int) -> dict:
 def reconstruct(ysub: np.ndarray, it: Iteration, P: Plan):
     """One iteration's reconstruction (Sec. 3.2) from its bucket values after
     subtraction: singleton detection, location and verification of every
-    active bucket, one candidate per located position, and the Eq. 14
-    median estimate of each.  When several buckets locate the same position
-    (a coefficient in the transition band reaches neighbouring buckets), the
-    candidate of the bucket whose centre is nearest is kept, the smaller
-    bucket index on a tie: its window weight Ghat is the largest, so its
-    estimate divides the bucket's error by the most.  Returns
-    (cands {f: v}, active mask, located position per bucket or -1)."""
+    active bucket, and the Eq. 14 median estimate of each located position.
+    Verification accepts a position only from its home bucket, so each
+    position yields at most one candidate.  Returns (cands {f: v}, active
+    mask, located position per bucket or -1)."""
     N = P.N
     active = detect(ysub, it.B, P.eta, P.rho)
     located = np.full(it.B, -1, dtype=np.int64)
-    best: dict = {}
+    cands = {}
     for i in np.flatnonzero(active):
         i = int(i)
         th = phases(ysub, i)
@@ -425,12 +429,6 @@ def reconstruct(ysub: np.ndarray, it: Iteration, P: Plan):
         if not verify(th, u, i, it, N, P.l):
             continue
         located[i] = u
-        dist = min(abs(i * it.L - u), N - abs(i * it.L - u))
-        # buckets are visited in ascending order, so a tie keeps the smaller index
-        if u not in best or dist < best[u][0]:
-            best[u] = (dist, i)
-    cands = {}
-    for u, (dist, i) in best.items():
         f = (it.sigma_inv * u) % N
         cands[f] = estimate(ysub, i, u, it, N)
     return cands, active, located

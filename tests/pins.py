@@ -242,8 +242,9 @@ def check_p7_location(O, N=4096, B=64, lq=((16, Fraction(1)), (4, Fraction(1, 4)
                       delta=1e-8, seed=3):
     """P7 (Sec. 3.2, Eq. 16): a lone noiseless coefficient is located
     exactly, at every permuted position u (exhaustive by default) and from
-    every bucket whose extended region reaches it; verification accepts it,
-    and the result does not depend on the offset tau0."""
+    every bucket whose extended region reaches it; verification accepts it
+    in the bucket whose range [iL - L/2, iL + L/2) holds u (Lemma 1) and
+    nowhere else, and the result does not depend on the offset tau0."""
     w = (B * int(math.log2(N))) | 1
     for l, q in lq:
         P = O.make_plan(N, 1, B, w, 1, l, q, delta, seed=seed)
@@ -259,7 +260,9 @@ def check_p7_location(O, N=4096, B=64, lq=((16, Fraction(1)), (4, Fraction(1, 4)
                 th = O.phases(yh, i)
                 got = O.locate(th, i, it, N, l, q)
                 assert got == u, f"P7 (l={l}, q={q}) u={u} bucket {i}: located {got}"
-                assert O.verify(th, u, i, it, N, l), f"P7 verify rejected u={u} in bucket {i}"
+                # the range of bucket i: iL - L/2 <= u < iL + L/2 (circularly)
+                off = (u - i * it.L + it.L // 2) % N
+                assert O.verify(th, u, i, it, N, l) == (off < it.L), f"P7 verify of u={u} in bucket {i}"
         # tau0 invariance on a sample of positions
         it2 = O.make_plan(N, 1, B, w, 1, l, q, delta, seed=seed + 1000).iters[0]
         it2 = type(it)(**{**it.__dict__, "tau0": it2.tau0,
@@ -292,7 +295,8 @@ def check_p12_direct_location(O, N=4096, B=64, delta=1e-8, seed=5, us=None):
             th = O.phases(yh, i)
             got = O.locate(th, i, it, N, 16, Fraction(1))
             assert got == u, f"P12 u={u} bucket {i}: located {got}"
-            assert O.verify(th, u, i, it, N, 16), f"P12 verify rejected u={u} in bucket {i}"
+            off = (u - i * it.L + it.L // 2) % N
+            assert O.verify(th, u, i, it, N, 16) == (off < it.L), f"P12 verify of u={u} in bucket {i}"
     r = rng(seed)
     grid = 2 * math.pi * np.arange(N) / N
     for _ in range(200):
@@ -484,53 +488,54 @@ def _exact_phases(it, u, v, N, i):
 
 def check_p14_verify(O, N=4096, B=64, lq=((16, Fraction(1)), (4, Fraction(1, 4))), delta=1e-8, seed=17):
     """P14 (Eq. 18 bound, Sec. 3.2): a location is trusted only while every
-    round's phase error is at most half a block, pi/l, and the position lies
-    where the bucket's window reaches (|iL - u| <= L/2 + e).  For lone
-    coefficients at many positions and from every bucket that reaches them,
-    verify accepts the exact phases; it accepts a phase error of
+    round's phase error is at most half a block, pi/l, and only in the
+    bucket whose range holds the position (Lemma 1: u in [iL - L/2,
+    iL + L/2)).  For lone coefficients at many positions, from their home
+    bucket, verify accepts the exact phases; it accepts a phase error of
     (1 - 1e-9) pi/l in any one round, of either sign, and rejects
-    (1 + 1e-9) pi/l in any one round.  A position one step beyond the reach
-    is rejected even with exact phases; one exactly at the reach is kept."""
+    (1 + 1e-9) pi/l in any one round.  At the edges of the range, with exact
+    phases, iL - L/2 and iL + L/2 - 1 are kept and iL + L/2 and
+    iL - L/2 - 1 are rejected (they belong to the neighbours)."""
     w = (B * int(math.log2(N))) | 1
     r = rng(seed)
     v = complex(0.6, 0.8)
     for l, q in lq:
         it = O.make_plan(N, 1, B, w, 1, l, q, delta, seed=seed).iters[0]
         tol = math.pi / l
+        L = it.L
         for u in r.choice(N, size=40, replace=False).tolist():
-            for i_unwrapped in O.bucket_range(u, it.L, it.D):
-                i = i_unwrapped % B
-                th = _exact_phases(it, u, v, N, i)
-                assert O.verify(th, u, i, it, N, l), f"P14 exact phases rejected (u={u}, i={i})"
-                for j in range(1, it.R + 1):
-                    for sgn in (1.0, -1.0):
-                        inside = list(th)
-                        inside[j] = (th[j] + sgn * tol * (1 - 1e-9)) % TWO_PI
-                        assert O.verify(inside, u, i, it, N, l), f"P14 error inside pi/l rejected (l={l}, j={j})"
-                        outside = list(th)
-                        outside[j] = (th[j] + sgn * tol * (1 + 1e-9)) % TWO_PI
-                        assert not O.verify(outside, u, i, it, N, l), \
-                            f"P14 error beyond pi/l accepted (l={l}, j={j}, sign {sgn})"
-        # the reach: exact phases of a position at distance D and D + 1
+            i = ((u + L // 2) // L) % B
+            th = _exact_phases(it, u, v, N, i)
+            assert O.verify(th, u, i, it, N, l), f"P14 exact phases rejected (u={u}, i={i})"
+            for j in range(1, it.R + 1):
+                for sgn in (1.0, -1.0):
+                    inside = list(th)
+                    inside[j] = (th[j] + sgn * tol * (1 - 1e-9)) % TWO_PI
+                    assert O.verify(inside, u, i, it, N, l), f"P14 error inside pi/l rejected (l={l}, j={j})"
+                    outside = list(th)
+                    outside[j] = (th[j] + sgn * tol * (1 + 1e-9)) % TWO_PI
+                    assert not O.verify(outside, u, i, it, N, l), \
+                        f"P14 error beyond pi/l accepted (l={l}, j={j}, sign {sgn})"
+        # the edges of bucket i's range, with the exact phases bucket i sees
         for i in (0, 5, B - 1):
-            for side in (1, -1):
-                u_in = (i * it.L + side * it.D) % N
-                u_out = (i * it.L + side * (it.D + 1)) % N
-                assert O.verify(_exact_phases(it, u_in, v, N, i), u_in, i, it, N, l), "P14 reach edge rejected"
-                th = [0.0] + [TWO_PI * ((it.taus[j] * u_out) % N) / N for j in range(1, it.R + 1)]
-                assert not O.verify(th, u_out, i, it, N, l), "P14 position beyond the reach accepted"
+            for off, keep in ((-(L // 2), True), (L // 2 - 1, True), (L // 2, False), (-(L // 2) - 1, False)):
+                u = (i * L + off) % N
+                ok = O.verify(_exact_phases(it, u, v, N, i), u, i, it, N, l)
+                assert ok == keep, f"P14 position {off:+d} from the centre of bucket {i}: verify {ok}"
 
 
-def check_p15_dedupe(O, N=4096, B=64, delta=1e-8, seed=19):
-    """P15 (dedupe of one position seen by two buckets; Eq. 14 error
-    propagation): a lone coefficient v at u between the centres of buckets
-    i (distance 10) and i + 1 (distance L - 10), both within the window's
-    reach, is located from both.  Each bucket carries an error c, placed in
-    every round so that it shifts every round's Eq. 14 estimate by the same
-    amount c / Ghat: the estimate of bucket k is then exactly
-    v + c / Ghat_{d_k}.  The candidate kept must be the nearer bucket's,
-    within |c| / Ghat_10 (1e-12 relative), not the farther one's, which is
-    off by |c| / Ghat_{L-10} (orders of magnitude more)."""
+def check_p15_home_bucket(O, N=4096, B=64, delta=1e-8, seed=19):
+    """P15 (one position seen by two buckets; Eq. 14 error propagation): a
+    lone coefficient v at u between the centres of buckets i (distance 10)
+    and i + 1 (distance L - 10), both within the window's reach, is located
+    from both.  Each bucket carries an error c, placed in every round so
+    that it shifts every round's Eq. 14 estimate by the same amount
+    c / Ghat: the estimate of bucket k is then exactly v + c / Ghat_{d_k}.
+    The one candidate must be the home bucket's, within |c| / Ghat_10 (1e-12
+    relative), not the other's, which is off by |c| / Ghat_{L-10}, orders of
+    magnitude more: a position deep in a bucket's transition band, where
+    Ghat falls toward delta, would turn any error of that bucket into a
+    huge false coefficient."""
     w = (B * int(math.log2(N))) | 1
     P = O.make_plan(N, 1, B, w, 1, 16, 1, delta, seed=seed)
     it = P.iters[0]
@@ -552,12 +557,13 @@ def check_p15_dedupe(O, N=4096, B=64, delta=1e-8, seed=19):
             yh[:, k] += np.array([c * np.exp(-2j * np.pi * ((it.T[j] * u) % N) / N) for j in range(it.R + 1)])
         cands, active, located = O.reconstruct(yh, it, P)
         assert active[near] and active[far], "P15 both buckets must pass detection"
-        assert located[near] == u and located[far] == u, "P15 both buckets must locate u"
+        assert located[near] == u and located[far] == -1, "P15 only the home bucket keeps u"
         f = (it.sigma_inv * u) % N
         assert list(cands) == [f], f"P15 one candidate per position, got {sorted(cands)}"
         want = v + c / g_near
         assert abs(cands[f] - want) <= 1e-12 * abs(v), \
             f"P15 kept the farther bucket's estimate ({abs(cands[f] - v):.3g} from v)"
+        assert abs(c / g_far) > 10 * abs(cands[f] - v), "P15 the farther estimate must be far worse"
 
 
 def check_p16_eta_floor(O, N=4096, B=64, delta=1e-8, seed=23):

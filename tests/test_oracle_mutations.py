@@ -57,7 +57,7 @@ CHECKS = {
     "p12": lambda O: pins.check_p12_direct_location(O, us=range(0, 4096, 5)),
     "p13": lambda O: pins.check_p13_vote(O, _sig),
     "p14": pins.check_p14_verify,
-    "p15": pins.check_p15_dedupe,
+    "p15": pins.check_p15_home_bucket,
     "p16": pins.check_p16_eta_floor,
 }
 
@@ -139,14 +139,15 @@ MUTANTS = [
     ("((it.taus[j] * u) % N) / N) > math.pi / l:", "((it.taus[j] * u) % N) / N) > 2 * math.pi / l:", ["p14"]),
     # verify: tolerance a quarter block
     ("((it.taus[j] * u) % N) / N) > math.pi / l:", "((it.taus[j] * u) % N) / N) > 0.5 * math.pi / l:", ["p14"]),
-    # verify: the reach check dropped
-    ("    if dist > it.D:\n        return False\n    for j", "    for j", ["p14"]),
-    # verify: the reach one position short
-    ("    if dist > it.D:\n        return False\n    for j", "    if dist >= it.D:\n        return False\n    for j", ["p14"]),
-    # dedupe: the farther bucket centre wins
-    ("if u not in best or dist < best[u][0]:", "if u not in best or dist > best[u][0]:", ["p15"]),
-    # dedupe: the last bucket that located the position wins
-    ("if u not in best or dist < best[u][0]:", "if True:", ["p15"]),
+    # verify: the home-bucket check dropped (any bucket that locates u keeps it)
+    ("    if home_bucket(u, it.L, it.B) != i:\n        return False\n", "", ["p14", "p15", "p7"]),
+    # verify: accepted wherever the window reaches (L/2 + e) instead of the home range
+    ("    if home_bucket(u, it.L, it.B) != i:\n        return False\n",
+     "    if min(abs(i * it.L - u), N - abs(i * it.L - u)) > it.D:\n        return False\n", ["p14", "p15", "p7"]),
+    # home bucket: halves rounded down instead of up
+    ("return ((u + L // 2) // L) % B", "return ((u + L // 2 - 1) // L) % B", ["p14", "p7"]),
+    # home bucket: the floor of u / L (no rounding to the nearest centre)
+    ("return ((u + L // 2) // L) % B", "return (u // L) % B", ["p14", "p7"]),
     # detection: the relative floor eta dropped
     ("thr = max(2.0 * math.log(B) * nu, eta * eta * float(p0.max()))", "thr = 2.0 * math.log(B) * nu", ["p16"]),
     # detection: the noise threshold dropped (only the relative floor left)

@@ -137,12 +137,12 @@ def test_p13_vote():
     pins.check_p13_vote(O, _signal)
 
 
-def test_p14_verify_bound_and_reach():
+def test_p14_verify_bound_and_home_range():
     pins.check_p14_verify(O)
 
 
-def test_p15_dedupe_nearest_bucket():
-    pins.check_p15_dedupe(O)
+def test_p15_home_bucket_only():
+    pins.check_p15_home_bucket(O)
 
 
 def test_p16_detection_floor():
