@@ -45,7 +45,7 @@ typedef enum {
   SFFT_ERR_UNSUPPORTED = 2,  /* valid per the paper, but beyond this library's limits */
   SFFT_ERR_ALLOC = 3,        /* device or host allocation failed */
   SFFT_ERR_LAUNCH = 4,       /* a HIP call or kernel launch failed */
-  SFFT_ERR_CAPACITY = 5,     /* recovered-coefficient store overflowed (count reads -1) */
+  SFFT_ERR_CAPACITY = 5,     /* a workspace exceeds a fixed capacity (sfft_execute_noalloc)  */
   SFFT_ERR_STATE = 6         /* object used in a state that does not allow the call */
 } sfft_status;
 
@@ -144,9 +144,7 @@ sfft_status sfft_plan(sfft_plan_t* out, int64_t N, int64_t K, int64_t B, int64_t
  *   scale   F16X2_SCALED only: the sample value is scale * d_x[j]; ignored otherwise.
  *   d_idx   K int64: recovered frequencies, ascending.
  *   d_val   K complex (float2, or double2 for C128): their values.
- *   d_count 1 int64: number of valid outputs (<= K), or -1 if the
- *           recovered-coefficient store overflowed (SFFT_ERR_CAPACITY on
- *           the device side; never happens with the default capacity).
+ *   d_count 1 int64: number of valid outputs (<= K).
  * Entries of d_idx/d_val beyond *d_count are left untouched.
  */
 sfft_status sfft_execute(sfft_plan_t p, const void* d_x, float scale, int64_t* d_idx, void* d_val,
@@ -277,10 +275,13 @@ sfft_status sfft_execute_interleaved(sfft_batch_t b, const void* d_x, int64_t ld
 /*
  * sfft_batch_launch_stage -- enqueue one stage of the batch on `stream`, for
  * timing the stages separately (the sequence fold, bucket DFT, recover is
- * exactly what sfft_execute_batch replays):
+ * exactly what sfft_execute_batch replays in SFFT_BATCH_STAGES mode):
  *   stage 0: permuted gather + window + fold (HashToBins, Eq. 7, 10, 11)
  *   stage 1: B-point DFT of every round (Eq. 12 with the 1/N factor)
  *   stage 2: recovery (subtraction .. top-K)
+ *   stage 3: the whole step as one persistent launch (SFFT_BATCH_FUSED, see
+ *            sfft_batch_tuning); SFFT_ERR_UNSUPPORTED when the batch cannot
+ *            run it.
  * Uses the buffers bound by the last execute of the batch (SFFT_ERR_STATE if
  * none).
  */
@@ -308,13 +309,59 @@ sfft_status sfft_plan_set_fold_config(sfft_plan_t p, const sfft_fold_config* cfg
 sfft_status sfft_batch_set_fold_config(sfft_batch_t b, const sfft_fold_config* cfg);
 
 /*
- * sfft_batch_autotune -- time the fold stage of the bound batch (buffers
- * bound by a prior sfft_execute_batch) for every unroll x wg_per_cu
- * candidate on `stream`, keep the fastest and report it in *best.  Blocks
- * until the timing launches finish.  The timing launches overwrite the
- * batch's bucket workspace only (outputs are untouched); the batch's graph
- * is captured again by the next sfft_execute_batch.  SFFT_ERR_STATE when no
- * buffers are bound.
+ * How a batch runs (sfft_batch_get_tuning / sfft_batch_set_tuning):
+ *   SFFT_BATCH_STAGES  three launches replayed from a graph: the fold stage
+ *                      (taps in flight fold_unroll = 8, 16 or 24; residency
+ *                      cap fold_wg_per_cu = 0 or 2..8, per-signal layout
+ *                      only), the bucket DFTs (fft_group_points = 1024, 2048
+ *                      or 4096 points per workgroup when B is smaller), and
+ *                      the recovery;
+ *   SFFT_BATCH_FUSED   one persistent launch (after a small kernel that
+ *                      clears its counters), also replayed from a graph: the
+ *                      workgroups take fold tiles and per-signal finish items
+ *                      (bucket DFTs, then recovery) from a queue ordered in
+ *                      chunks of fused_chunk signals (per-signal layout) or
+ *                      groups of 64 signals (position-major); a signal's
+ *                      finish item waits for its fold tiles, so the recovery
+ *                      of early signals overlaps the gather of later ones.
+ *                      Available when every round of every plan (B_m complex
+ *                      values) fits in 78,848 bytes: B <= 8192 for complex64
+ *                      and FP16 storage, B <= 4096 for complex128.  A wait
+ *                      that has not ended after a bounded number of polls
+ *                      (seconds) gives up: that signal's count reads -2.
+ * Every setting gives bit-identical results.  Setting a tuning waits for the
+ * batch's last replay and drops its graph, like sfft_batch_set_fold_config.
+ * SFFT_ERR_PARAM for a value outside the lists, or (FUSED) fused_chunk
+ * outside 1 .. the number of signals (or groups); SFFT_ERR_UNSUPPORTED for
+ * FUSED where it is not available.
+ */
+typedef enum { SFFT_BATCH_STAGES = 0, SFFT_BATCH_FUSED = 1 } sfft_batch_mode;
+typedef struct {
+  int32_t mode;             /* sfft_batch_mode */
+  int32_t fused_chunk;      /* FUSED: signals (per-signal layout) or groups of 64 signals per chunk */
+  int32_t fold_unroll;      /* STAGES: fold taps in flight */
+  int32_t fold_wg_per_cu;   /* STAGES: fold residency cap */
+  int32_t fft_group_points; /* STAGES: bucket-DFT points per workgroup */
+  int32_t fused_available;  /* read only: 1 if the batch can run FUSED */
+  double step_ms;           /* read only: one step of this configuration, as sfft_batch_autotune timed it */
+} sfft_batch_tuning;
+sfft_status sfft_batch_get_tuning(sfft_batch_t b, sfft_batch_tuning* t);
+sfft_status sfft_batch_set_tuning(sfft_batch_t b, const sfft_batch_tuning* t);
+
+/*
+ * sfft_batch_autotune -- choose how the bound batch (buffers bound by a prior
+ * execute) runs, by timing launches on `stream`: first the fold stage for
+ * every unroll x wg_per_cu candidate, then the bucket DFT for every
+ * fft_group_points candidate, then one whole step of the three stages
+ * against the fused launch at four chunk sizes; the fastest step wins.
+ * *best receives the fold choice (fold_ms: its mean fold time);
+ * sfft_batch_get_tuning gives the whole choice.  The choice is kept for the
+ * life of the process per batch shape (dtype, Kahan, layout, number of
+ * signals and every plan's N, B, w, loops, l and combine): a later call on a
+ * batch of the same shape applies it without timing.  Blocks until the
+ * timing launches finish; they rewrite the batch's workspace and outputs
+ * with the values an execute gives.  The graph is captured again by the
+ * next execute.  SFFT_ERR_STATE when no buffers are bound.
  */
 sfft_status sfft_batch_autotune(sfft_batch_t b, void* stream, sfft_fold_config* best);
 

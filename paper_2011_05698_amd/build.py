@@ -13,7 +13,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libsfft.so")
 
-SOURCES = ["plan.cpp", "api.hip", "fold.hip", "bucket_fft.hip", "recover.hip"]
+SOURCES = ["plan.cpp", "api.hip", "fold.hip", "bucket_fft.hip", "recover.hip", "fused.hip"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950",

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
@@ -105,6 +106,21 @@ struct sfft_batch_s {
   FoldConfig fold{8, 0};
   bool interleaved = false;         // one plan, position-major signals (sfft_batch_create_interleaved)
   uint32_t ngroups = 0;             // interleaved: signal groups of kIlvSigs
+  // bucket-DFT grouping: round items (host copy) cut into groups of at most fft_group_points points
+  std::vector<RoundItem> h_items;
+  uint32_t fft_group_points = kFftGroupPoints;
+  // the fused persistent launch (fused.hip)
+  int mode = SFFT_BATCH_STAGES;
+  bool fused_ok = false;            // every plan's largest round fits the fused kernel's LDS
+  uint32_t fused_chunk = 1;         // counter groups per chunk of the item order
+  std::vector<std::vector<FoldTile>> group_tiles;  // fold tiles of each counter group, in launch order
+  FusedItem* d_fitems = nullptr;
+  uint32_t nfitems = 0;
+  uint32_t* d_ctl = nullptr;        // queue head, waits that gave up, per-group counters
+  uint32_t* d_need = nullptr;
+  uint32_t nfgroups = 0;            // counter groups: signals, or signal groups (position-major)
+  uint32_t fused_grid = 0;
+  float step_ms = 0.f;              // the autotuner's time of the chosen configuration
 };
 
 namespace {
@@ -124,14 +140,15 @@ uint64_t align256(uint64_t v) { return (v + 255) & ~uint64_t(255); }
 // Orders round items by B (largest first, stable) and cuts them into
 // bucket-DFT workgroups of equal B and at most kFftGroupPoints points.
 template <class BOf>
-void group_rounds(std::vector<RoundItem>& items, BOf b_of, std::vector<FftGroup>& groups, uint32_t& max_points) {
+void group_rounds(std::vector<RoundItem>& items, BOf b_of, std::vector<FftGroup>& groups, uint32_t& max_points,
+                  uint32_t points = kFftGroupPoints) {
   std::stable_sort(items.begin(), items.end(),
                    [&](const RoundItem& x, const RoundItem& y) { return b_of(x) > b_of(y); });
   groups.clear();
   max_points = 0;
   for (uint32_t a = 0; a < uint32_t(items.size());) {
     const uint32_t B = b_of(items[a]);
-    const uint32_t cap = std::max<uint32_t>(1u, kFftGroupPoints / B);
+    const uint32_t cap = std::max<uint32_t>(1u, points / B);
     uint32_t c = 1;
     while (a + c < uint32_t(items.size()) && c < cap && b_of(items[a + c]) == B) ++c;
     groups.push_back(FftGroup{a, c});
@@ -308,6 +325,53 @@ SigArg table_arg(const sfft_batch_s* b) {
   std::memset(&a, 0, sizeof(a));
   a.table = b->d_sigs;
   return a;
+}
+
+// The fused launch's work items: per chunk of `chunk` counter groups, every
+// fold tile of the chunk's groups, then the finish item of each of their
+// signals.
+void build_fused_items(const sfft_batch_s* b, uint32_t chunk, std::vector<FusedItem>& out) {
+  out.clear();
+  const uint32_t nsig = uint32_t(b->plans.size());
+  for (uint32_t g0 = 0; g0 < b->nfgroups; g0 += chunk) {
+    const uint32_t g1 = std::min(b->nfgroups, g0 + chunk);
+    for (uint32_t g = g0; g < g1; ++g)
+      for (const FoldTile& t : b->group_tiles[g]) out.push_back(FusedItem{kFusedFold, t.sig, t.m, t.i0});
+    const uint32_t s0 = b->interleaved ? g0 * kIlvSigs : g0;
+    const uint32_t s1 = std::min(nsig, b->interleaved ? g1 * kIlvSigs : g1);
+    for (uint32_t s = s0; s < s1; ++s) out.push_back(FusedItem{kFusedFinish, s, 0, 0});
+  }
+}
+
+FusedArgs fused_args(const sfft_batch_s* b) {
+  FusedArgs a;
+  a.table = b->d_sigs;
+  a.nsig = uint32_t(b->plans.size());
+  a.nitems = b->nfitems;
+  a.items = b->d_fitems;
+  a.ctl = b->d_ctl;
+  a.need = b->d_need;
+  return a;
+}
+
+int launch_batch_fused(const sfft_batch_s* b, hipStream_t s) {
+  return launch_fused(b->dtype, b->kahan, b->interleaved, b->fused_grid, 2 + b->nfgroups, fused_args(b), s);
+}
+
+// Cuts the round items into bucket-DFT groups of at most `points` points and
+// uploads them (synchronously).
+sfft_status regroup_fft(sfft_batch_s* b, uint32_t points) {
+  std::vector<RoundItem> items = b->h_items;
+  std::vector<FftGroup> groups;
+  uint32_t maxp = 0;
+  group_rounds(items, [&](const RoundItem& r) { return b->plans[r.sig]->hp.iters[r.m].d.B; }, groups, maxp, points);
+  hipError_t e = hipMemcpy(b->d_items, items.data(), sizeof(RoundItem) * items.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(b->d_groups, groups.data(), sizeof(FftGroup) * groups.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "bucket-DFT groups upload");
+  b->nfft = uint32_t(groups.size());
+  b->fft_points = maxp;
+  b->fft_group_points = points;
+  return SFFT_OK;
 }
 
 int launch_batch_fold(const sfft_batch_s* b, const FoldConfig& cfg, hipStream_t s) {
@@ -541,38 +605,68 @@ sfft_status create_batch_impl(sfft_batch_t* out, const sfft_plan_t* h_plans, int
   std::vector<FoldTile> tiles;
   std::vector<RoundItem> items;
   uint64_t ws = 0;
+  const uint32_t cb = b->dtype == SFFT_C128 ? 16u : 8u;
+  b->fused_ok = true;
   for (int32_t s = 0; s < n; ++s) {
     const HostPlan& hp = h_plans[s]->hp;
+    const size_t t0 = tiles.size();
     build_work_lists(hp, uint32_t(s), tiles, items);
+    if (!interleaved) b->group_tiles.emplace_back(tiles.begin() + t0, tiles.end());
     b->ws_off.push_back(ws);
     ws += align256(hp.desc.ws_bytes);
     b->max_B = std::max(b->max_B, max_B(hp));
+    if (uint64_t(max_B(hp)) * cb > kRecoverLdsBytes) b->fused_ok = false;
   }
   if (interleaved) {
     b->ngroups = uint32_t((n + kIlvSigs - 1) / kIlvSigs);
     tiles.clear();
     interleaved_tiles(h_plans[0]->hp, b->ngroups, tiles);
+    b->group_tiles.resize(b->ngroups);
+    for (const FoldTile& t : tiles) b->group_tiles[t.sig].push_back(t);
   }
+  b->nfgroups = uint32_t(b->group_tiles.size());
+  b->h_items = items;
   std::vector<FftGroup> groups;
   group_rounds(items, [&](const RoundItem& r) { return h_plans[r.sig]->hp.iters[r.m].d.B; }, groups, b->fft_points);
   b->ntiles = uint32_t(tiles.size());
   b->nitems = uint32_t(items.size());
   b->nfft = uint32_t(groups.size());
+  // the fused launch: one chunk per signal group (position-major) or per 32 signals
+  b->fused_chunk = interleaved ? 1u : std::min<uint32_t>(32u, uint32_t(n));
+  std::vector<FusedItem> fitems;
+  build_fused_items(b, b->fused_chunk, fitems);
+  b->nfitems = uint32_t(fitems.size());
+  std::vector<uint32_t> need(b->nfgroups);
+  for (uint32_t g = 0; g < b->nfgroups; ++g) need[g] = uint32_t(b->group_tiles[g].size());
+  int dev = 0, ncu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return hip_fail(e, "device attributes");
+  b->fused_grid = uint32_t(std::max(1, ncu)) * 2u;  // two workgroups of the fused kernel fit a compute unit
   const uint64_t o_sigs = 0;
   const uint64_t o_tiles = align256(sizeof(SignalDesc) * n);
   const uint64_t o_items = o_tiles + align256(sizeof(FoldTile) * tiles.size());
   const uint64_t o_groups = o_items + align256(sizeof(RoundItem) * items.size());
-  const uint64_t o_ws = o_groups + align256(sizeof(FftGroup) * groups.size());
-  hipError_t e = dev_malloc(reinterpret_cast<void**>(&b->d_mem), o_ws + ws);
+  // room for the smallest grouping (one round per group)
+  const uint64_t o_fitems = o_groups + align256(sizeof(FftGroup) * items.size());
+  const uint64_t o_ctl = o_fitems + align256(sizeof(FusedItem) * fitems.size());
+  const uint64_t o_need = o_ctl + align256(sizeof(uint32_t) * (2 + b->nfgroups));
+  const uint64_t o_ws = o_need + align256(sizeof(uint32_t) * b->nfgroups);
+  e = dev_malloc(reinterpret_cast<void**>(&b->d_mem), o_ws + ws);
   if (e != hipSuccess) return hip_fail(e, "hipMalloc(batch)");
   b->d_sigs = reinterpret_cast<SignalDesc*>(b->d_mem + o_sigs);
   b->d_tiles = reinterpret_cast<FoldTile*>(b->d_mem + o_tiles);
   b->d_items = reinterpret_cast<RoundItem*>(b->d_mem + o_items);
   b->d_groups = reinterpret_cast<FftGroup*>(b->d_mem + o_groups);
+  b->d_fitems = reinterpret_cast<FusedItem*>(b->d_mem + o_fitems);
+  b->d_ctl = reinterpret_cast<uint32_t*>(b->d_mem + o_ctl);
+  b->d_need = reinterpret_cast<uint32_t*>(b->d_mem + o_need);
   b->d_ws = b->d_mem + o_ws;
   e = hipMemcpy(b->d_tiles, tiles.data(), sizeof(FoldTile) * tiles.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(b->d_items, items.data(), sizeof(RoundItem) * items.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(b->d_groups, groups.data(), sizeof(FftGroup) * groups.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(b->d_fitems, fitems.data(), sizeof(FusedItem) * fitems.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(b->d_need, need.data(), sizeof(uint32_t) * need.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->replayed, hipEventDisableTiming);
   if (e != hipSuccess) {
@@ -618,9 +712,14 @@ sfft_status bind_and_replay(sfft_batch_t b, const std::vector<SignalDesc>& sig, 
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
     const SigArg a = table_arg(b);
-    int le = launch_batch_fold(b, b->fold, cs);
-    if (le == hipSuccess) le = launch_bucket_fft(b->dtype, a, b->d_items, b->d_groups, b->nfft, b->fft_points, cs);
-    if (le == hipSuccess) le = launch_recover(b->dtype, a, uint32_t(n), cs);
+    int le;
+    if (b->mode == SFFT_BATCH_FUSED) {
+      le = launch_batch_fused(b, cs);
+    } else {
+      le = launch_batch_fold(b, b->fold, cs);
+      if (le == hipSuccess) le = launch_bucket_fft(b->dtype, a, b->d_items, b->d_groups, b->nfft, b->fft_points, cs);
+      if (le == hipSuccess) le = launch_recover(b->dtype, a, uint32_t(n), cs);
+    }
     hipGraph_t g = nullptr;
     hipError_t ee = hipStreamEndCapture(cs, &g);
     if (le != hipSuccess) return hip_fail(hipError_t(le), "batch capture launch");
@@ -694,6 +793,19 @@ sfft_status sfft_execute_interleaved(sfft_batch_t b, const void* d_x, int64_t ld
   return bind_and_replay(b, sig, reinterpret_cast<hipStream_t>(stream));
 }
 
+// Drops the batch's captured graph once its last replay has ended (an event on
+// the caller's stream); the next execute captures again.
+static sfft_status drop_graph(sfft_batch_t b) {
+  if (!b->exec && !b->graph) return SFFT_OK;
+  const hipError_t e = b->replay_recorded ? hipEventSynchronize(b->replayed) : hipSuccess;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+  return SFFT_OK;
+}
+
 sfft_status sfft_batch_launch_stage(sfft_batch_t b, int32_t stage, void* stream) {
   if (!b) return fail(SFFT_ERR_PARAM, "null batch");
   if (!b->has_binding) return fail(SFFT_ERR_STATE, "no buffers bound: execute the batch first");
@@ -704,7 +816,11 @@ sfft_status sfft_batch_launch_stage(sfft_batch_t b, int32_t stage, void* stream)
     case 0: e = launch_batch_fold(b, b->fold, s); break;
     case 1: e = launch_bucket_fft(b->dtype, a, b->d_items, b->d_groups, b->nfft, b->fft_points, s); break;
     case 2: e = launch_recover(b->dtype, a, uint32_t(b->plans.size()), s); break;
-    default: return fail(SFFT_ERR_PARAM, "stage must be 0, 1 or 2");
+    case 3:
+      if (!b->fused_ok) return fail(SFFT_ERR_UNSUPPORTED, "a round of this batch does not fit the fused kernel's LDS");
+      e = launch_batch_fused(b, s);
+      break;
+    default: return fail(SFFT_ERR_PARAM, "stage must be 0, 1, 2 or 3");
   }
   if (e != hipSuccess) return hip_fail(hipError_t(e), "stage launch");
   return SFFT_OK;
@@ -719,62 +835,196 @@ sfft_status sfft_plan_set_fold_config(sfft_plan_t p, const sfft_fold_config* cfg
 sfft_status sfft_batch_set_fold_config(sfft_batch_t b, const sfft_fold_config* cfg) {
   if (!b || !valid_fold(cfg)) return fail(SFFT_ERR_PARAM, "invalid fold configuration");
   b->fold = FoldConfig{cfg->unroll, cfg->wg_per_cu};
-  if (b->exec || b->graph) {
-    // the captured graph holds the old kernel choice: let this batch's last
-    // replay end (its event on the caller's stream), drop the graph, and
-    // capture again on the next execute
-    const hipError_t e = b->replay_recorded ? hipEventSynchronize(b->replayed) : hipSuccess;
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
-    b->exec = nullptr;
-    b->graph = nullptr;
-    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
-  }
+  return drop_graph(b);
+}
+
+sfft_status sfft_batch_get_tuning(sfft_batch_t b, sfft_batch_tuning* t) {
+  if (!b || !t) return fail(SFFT_ERR_PARAM, "null argument");
+  std::memset(t, 0, sizeof(*t));
+  t->mode = b->mode;
+  t->fused_chunk = int32_t(b->fused_chunk);
+  t->fold_unroll = b->fold.unroll;
+  t->fold_wg_per_cu = b->fold.wg_per_cu;
+  t->fft_group_points = int32_t(b->fft_group_points);
+  t->fused_available = b->fused_ok ? 1 : 0;
+  t->step_ms = double(b->step_ms);
   return SFFT_OK;
 }
+
+sfft_status sfft_batch_set_tuning(sfft_batch_t b, const sfft_batch_tuning* t) {
+  if (!b || !t) return fail(SFFT_ERR_PARAM, "null argument");
+  const sfft_fold_config fc{t->fold_unroll, t->fold_wg_per_cu, 0.0};
+  if (!valid_fold(&fc)) return fail(SFFT_ERR_PARAM, "invalid fold configuration");
+  if (t->mode != SFFT_BATCH_STAGES && t->mode != SFFT_BATCH_FUSED) return fail(SFFT_ERR_PARAM, "invalid mode");
+  if (t->mode == SFFT_BATCH_FUSED && !b->fused_ok)
+    return fail(SFFT_ERR_UNSUPPORTED, "a round of this batch does not fit the fused kernel's LDS");
+  if (t->mode == SFFT_BATCH_FUSED && (t->fused_chunk < 1 || uint32_t(t->fused_chunk) > b->nfgroups))
+    return fail(SFFT_ERR_PARAM, "fused_chunk must be in 1 .. the number of signals (or groups of 64)");
+  if (t->fft_group_points != 1024 && t->fft_group_points != 2048 && t->fft_group_points != 4096)
+    return fail(SFFT_ERR_PARAM, "fft_group_points must be 1024, 2048 or 4096");
+  sfft_status st = drop_graph(b);  // the device lists below are read by the last replay
+  if (st != SFFT_OK) return st;
+  if (uint32_t(t->fft_group_points) != b->fft_group_points) {
+    st = regroup_fft(b, uint32_t(t->fft_group_points));
+    if (st != SFFT_OK) return st;
+  }
+  if (t->mode == SFFT_BATCH_FUSED && uint32_t(t->fused_chunk) != b->fused_chunk) {
+    std::vector<FusedItem> items;
+    build_fused_items(b, uint32_t(t->fused_chunk), items);
+    const hipError_t e = hipMemcpy(b->d_fitems, items.data(), sizeof(FusedItem) * items.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "fused items upload");
+    b->fused_chunk = uint32_t(t->fused_chunk);
+  }
+  b->mode = t->mode;
+  b->fold = FoldConfig{t->fold_unroll, t->fold_wg_per_cu};
+  return SFFT_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Choices of the autotuner, per batch shape, for the life of the process.
+std::mutex g_tune_mu;
+std::map<std::string, sfft_batch_tuning> g_tune_cache;
+
+std::string tuning_key(const sfft_batch_s* b) {
+  std::string k = std::to_string(b->dtype) + "/" + std::to_string(b->kahan) + "/" + (b->interleaved ? "pm" : "ps") +
+                  "/" + std::to_string(b->plans.size());
+  uint64_t h = 1469598103934665603ull;  // FNV-1a over every plan's shape
+  for (const sfft_plan_t p : b->plans) {
+    const uint64_t v[6] = {uint64_t(p->hp.N), uint64_t(p->hp.B), uint64_t(p->hp.w), uint64_t(p->hp.loops),
+                           uint64_t(p->hp.l), uint64_t(p->hp.desc.combine)};
+    for (uint64_t x : v)
+      for (int i = 0; i < 8; ++i) h = (h ^ ((x >> (8 * i)) & 255u)) * 1099511628211ull;
+  }
+  return k + "/" + std::to_string(h);
+}
+
+// Mean time of `reps` launches of fn() on s (one warm-up first); negative on a launch error.
+template <class F>
+float time_launches(F fn, hipStream_t s, hipEvent_t e0, hipEvent_t e1, int reps, int* err) {
+  int le = fn();
+  float total = 0.f;
+  for (int r = 0; r < reps && le == hipSuccess; ++r) {
+    (void)hipEventRecord(e0, s);
+    le = fn();
+    (void)hipEventRecord(e1, s);
+    if (hipEventSynchronize(e1) != hipSuccess) le = hipErrorLaunchFailure;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    total += ms;
+  }
+  *err = le;
+  return total / float(reps);
+}
+
+}  // namespace
+
+extern "C" {
 
 sfft_status sfft_batch_autotune(sfft_batch_t b, void* stream, sfft_fold_config* best) {
   if (!b) return fail(SFFT_ERR_PARAM, "null batch");
   if (!b->has_binding) return fail(SFFT_ERR_STATE, "no buffers bound: execute the batch first");
+  const std::string key = tuning_key(b);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto hit = g_tune_cache.find(key);
+    if (hit != g_tune_cache.end()) {
+      sfft_status st = sfft_batch_set_tuning(b, &hit->second);
+      if (st != SFFT_OK) return st;
+      b->step_ms = float(hit->second.step_ms);
+      if (best) *best = sfft_fold_config{b->fold.unroll, b->fold.wg_per_cu, 0.0};
+      return SFFT_OK;
+    }
+  }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  sfft_status st = drop_graph(b);
+  if (st != SFFT_OK) return st;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return fail(SFFT_ERR_LAUNCH, "hipEventCreate");
+  int err = hipSuccess;
+  const SigArg a = table_arg(b);
+  // 1. fold launch shape: taps in flight x residency cap (per-signal layout only)
   const int unrolls[3] = {8, 16, 24};
   const int caps[5] = {0, 2, 3, 4, 6};
   const int ncaps = b->interleaved ? 1 : 5;  // the position-major fold has no residency cap
   FoldConfig win = b->fold;
-  float win_ms = 1e30f;
-  sfft_status st = SFFT_OK;
-  for (int ui = 0; ui < 3 && st == SFFT_OK; ++ui) {
-    for (int ci = 0; ci < ncaps && st == SFFT_OK; ++ci) {
+  float fold_ms = 1e30f;
+  for (int ui = 0; ui < 3 && err == hipSuccess; ++ui)
+    for (int ci = 0; ci < ncaps && err == hipSuccess; ++ci) {
       const FoldConfig c{unrolls[ui], caps[ci]};
-      int le = launch_batch_fold(b, c, s);  // warm
-      float total = 0.f;
-      for (int r = 0; r < 3 && le == hipSuccess; ++r) {
-        (void)hipEventRecord(e0, s);
-        le = launch_batch_fold(b, c, s);
-        (void)hipEventRecord(e1, s);
-        if (hipEventSynchronize(e1) != hipSuccess) le = hipErrorLaunchFailure;
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        total += ms;
-      }
-      if (le != hipSuccess) {
-        st = hip_fail(hipError_t(le), "autotune launch");
-        break;
-      }
-      if (total / 3.f < win_ms) {
-        win_ms = total / 3.f;
+      const float ms = time_launches([&] { return launch_batch_fold(b, c, s); }, s, e0, e1, 3, &err);
+      if (err == hipSuccess && ms < fold_ms) {
+        fold_ms = ms;
         win = c;
+      }
+    }
+  b->fold = win;
+  // 2. bucket-DFT workgroup size
+  uint32_t fft_win = b->fft_group_points;
+  float fft_ms = 1e30f;
+  for (uint32_t pts : {1024u, 2048u, 4096u}) {
+    if (err != hipSuccess) break;
+    st = regroup_fft(b, pts);
+    if (st != SFFT_OK) break;
+    const float ms = time_launches(
+        [&] { return launch_bucket_fft(b->dtype, a, b->d_items, b->d_groups, b->nfft, b->fft_points, s); }, s, e0, e1, 3,
+        &err);
+    if (err == hipSuccess && ms < fft_ms) {
+      fft_ms = ms;
+      fft_win = pts;
+    }
+  }
+  if (st == SFFT_OK && err == hipSuccess) st = regroup_fft(b, fft_win);
+  // 3. the whole step: the three stage launches against the fused launch at
+  //    several chunk sizes
+  sfft_batch_tuning tw{};
+  tw.mode = SFFT_BATCH_STAGES;
+  tw.fold_unroll = win.unroll;
+  tw.fold_wg_per_cu = win.wg_per_cu;
+  tw.fft_group_points = int32_t(fft_win);
+  tw.fused_chunk = int32_t(b->fused_chunk);
+  float step = 1e30f;
+  if (st == SFFT_OK && err == hipSuccess) {
+    step = time_launches(
+        [&] {
+          int le = launch_batch_fold(b, b->fold, s);
+          if (le == hipSuccess) le = launch_bucket_fft(b->dtype, a, b->d_items, b->d_groups, b->nfft, b->fft_points, s);
+          if (le == hipSuccess) le = launch_recover(b->dtype, a, uint32_t(b->plans.size()), s);
+          return le;
+        },
+        s, e0, e1, 3, &err);
+  }
+  if (b->fused_ok && st == SFFT_OK && err == hipSuccess) {
+    const uint32_t base = b->interleaved ? 1u : 16u;
+    for (uint32_t ch : {base, 2 * base, 4 * base, 8 * base}) {
+      if (ch > b->nfgroups || err != hipSuccess || st != SFFT_OK) break;
+      sfft_batch_tuning t = tw;
+      t.mode = SFFT_BATCH_FUSED;
+      t.fused_chunk = int32_t(ch);
+      st = sfft_batch_set_tuning(b, &t);
+      if (st != SFFT_OK) break;
+      const float ms = time_launches([&] { return launch_batch_fused(b, s); }, s, e0, e1, 3, &err);
+      if (err == hipSuccess && ms < step) {
+        step = ms;
+        tw = t;
       }
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  if (err != hipSuccess) return hip_fail(hipError_t(err), "autotune launch");
   if (st != SFFT_OK) return st;
-  sfft_fold_config out{win.unroll, win.wg_per_cu, double(win_ms)};
-  sfft_batch_set_fold_config(b, &out);
-  if (best) *best = out;
+  tw.step_ms = double(step);
+  st = sfft_batch_set_tuning(b, &tw);
+  if (st != SFFT_OK) return st;
+  b->step_ms = step;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = tw;
+  }
+  if (best) *best = sfft_fold_config{win.unroll, win.wg_per_cu, double(fold_ms)};
   return SFFT_OK;
 }
 

@@ -1,179 +1,19 @@
-// HashToBins, part 1 (Sec. 2.4, Lemma 1): permuted gather x[sigma (t - T) mod N]
-// (Eq. 7), window G_t (Eq. 10) and aliasing t -> t mod B (Eq. 11):
-//   y_j[b] = sum_{|t| <= h, t = b mod B} G_t x[sigma (t - T_j) mod N].
-// One thread owns one (round j, bucket b) item of an iteration and walks its
-// taps t = t_first + k B; the sample index advances by sigma B mod N per tap.
-// Index arithmetic is uint32 with wrap-around, exact because N divides 2^32.
-// Taps are fetched U at a time (predicated at the end) so that U independent
-// gathers are in flight per thread.
-#include "device_common.h"
+// Stage kernels of the fold: one workgroup per tile (device bodies in fold_body.h).
+#include "fold_body.h"
 
 namespace sfft {
 
-struct LoadC64 {
-  using R = float;
-  static constexpr bool kScaled = false;
-  static __device__ __forceinline__ cplx<float> load(const void* x, uint64_t i) {
-    return reinterpret_cast<const cplx<float>*>(x)[i];
-  }
-};
-struct LoadC128 {
-  using R = double;
-  static constexpr bool kScaled = false;
-  static __device__ __forceinline__ cplx<double> load(const void* x, uint64_t i) {
-    return reinterpret_cast<const cplx<double>*>(x)[i];
-  }
-};
-struct LoadF16 {
-  using R = float;
-  static constexpr bool kScaled = true;
-  typedef _Float16 h2 __attribute__((ext_vector_type(2)));
-  static __device__ __forceinline__ cplx<float> load(const void* x, uint64_t i) {
-    const h2 v = reinterpret_cast<const h2*>(x)[i];
-    return {float(v.x), float(v.y)};
-  }
-};
-
-template <typename R, bool KAHAN>
-struct Acc {
-  R re = 0, im = 0, cre = 0, cim = 0;
-  __device__ __forceinline__ void add(R g, cplx<R> s) {
-    if (KAHAN) {  // compensated summation (Kahan)
-      const R yr = g * s.re - cre;
-      const R tr = re + yr;
-      cre = (tr - re) - yr;
-      re = tr;
-      const R yi = g * s.im - cim;
-      const R ti = im + yi;
-      cim = (ti - im) - yi;
-      im = ti;
-    } else {
-      re += g * s.re;
-      im += g * s.im;
-    }
-  }
-};
-
 template <class Ld, bool KAHAN, int U>
 __global__ __launch_bounds__(kFoldTile) void fold_kernel(SigArg arg, const FoldTile* __restrict__ tiles) {
-  using R = typename Ld::R;
   const FoldTile tl = tiles[blockIdx.x];
-  const SignalDesc sd = load_signal(arg, tl.sig);
-  const PlanDesc* pd = sd.plan;
-  const IterDesc* it = pd->iters + tl.m;
-  const uint32_t B = it->B, logB = it->logB;
-  const uint32_t item = tl.i0 + threadIdx.x;
-  if (item >= ((it->R + 1) << logB)) return;
-  const uint32_t j = item >> logB, b = item & (B - 1);
-  const uint32_t nmask = pd->N - 1;
-  const int32_t h = int32_t(it->h);
-  const uint32_t T = it->T[j];
-  const uint32_t sigma = it->sigma;
-  const R* __restrict__ G = reinterpret_cast<const R*>(pd->window) + it->win_off;
-  // first tap t = b (mod B) with t >= -h; B <= w guarantees t_first <= h
-  const int32_t tf = -h + int32_t((b + uint32_t(h)) & (B - 1));
-  const uint32_t ntaps = uint32_t(h - tf) / B + 1;
-  uint32_t idx = (sigma * (uint32_t(tf) - T)) & nmask;
-  const uint32_t step = (sigma * B) & nmask;
-  Acc<R, KAHAN> acc;
-  int32_t t = tf;
-  for (uint32_t k0 = 0; k0 < ntaps; k0 += U) {
-    cplx<R> s[U];
-    R g[U];
-#pragma unroll
-    for (int q = 0; q < U; ++q) {
-      if (k0 + q < ntaps) {
-        s[q] = Ld::load(sd.x, idx);
-        g[q] = G[t < 0 ? -t : t];
-      } else {
-        s[q] = cplx<R>{0, 0};
-        g[q] = R(0);
-      }
-      idx = (idx + step) & nmask;
-      t += int32_t(B);
-    }
-#pragma unroll
-    for (int q = 0; q < U; ++q)
-      if (!KAHAN || k0 + q < ntaps) acc.add(g[q], s[q]);  // padded taps add exact zeros
-  }
-  cplx<R> out{acc.re, acc.im};
-  if (Ld::kScaled) out = cscale(out, R(sd.scale));
-  cplx<R>* Y = reinterpret_cast<cplx<R>*>(sd.y) + it->y_off;
-  Y[item] = out;  // item = j * B + b: row j of the iteration's (R+1) x B block
+  fold_tile<Ld, KAHAN, U>(load_signal(arg, tl.sig), tl);
 }
 
-// Position-major batch: the signals share one plan and sample c of signal s
-// sits at x_s + c * ld with x_s = x_0 + s, so for a given tap the 64 signals
-// of a workgroup are 64 adjacent elements of one row.  Lanes are signals and
-// each wave walks the taps of kIlvItems / 4 items: index, tap weight and
-// loop bounds are wave-uniform (scalar), every gather is one contiguous
-// row segment, and the sum for each (item, signal) takes the taps in the same
-// order and arithmetic as fold_kernel.  The kIlvItems x 64 results are
-// transposed through LDS so that each signal's consecutive items are written
-// as one contiguous run.
 template <class Ld, bool KAHAN, int U>
 __global__ __launch_bounds__(256) void fold_interleaved_kernel(const SignalDesc* __restrict__ table, uint32_t nsig,
                                                                const FoldTile* __restrict__ tiles) {
-  using R = typename Ld::R;
-  constexpr int kPerWave = kIlvItems / 4;
-  __shared__ cplx<R> tile[kIlvItems][kIlvSigs + 1];
-  __shared__ cplx<R>* ys[kIlvSigs];
-  const FoldTile tl = tiles[blockIdx.x];
-  const uint32_t lane = threadIdx.x & 63;
-  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const uint32_t s0 = tl.sig * kIlvSigs, s = s0 + lane;
-  const bool live = s < nsig;
-  const SignalDesc& head = table[s0];
-  const PlanDesc* pd = head.plan;
-  const IterDesc* it = pd->iters + tl.m;
-  const uint64_t ld = head.ld;
-  const char* xs = live ? reinterpret_cast<const char*>(table[s].x) : nullptr;
-  const R scale = live ? R(table[s].scale) : R(0);
-  if (wave == 0) ys[lane] = live ? reinterpret_cast<cplx<R>*>(table[s].y) + it->y_off : nullptr;
-  const uint32_t B = it->B, logB = it->logB;
-  const uint32_t nmask = pd->N - 1;
-  const int32_t h = int32_t(it->h);
-  const uint32_t sigma = it->sigma;
-  const uint32_t step = (sigma * B) & nmask;
-  const R* __restrict__ G = reinterpret_cast<const R*>(pd->window) + it->win_off;
-  for (int q = 0; q < kPerWave; ++q) {
-    const uint32_t item = tl.i0 + wave * kPerWave + q;
-    const uint32_t j = item >> logB, b = item & (B - 1);
-    const uint32_t T = it->T[j];
-    const int32_t tf = -h + int32_t((b + uint32_t(h)) & (B - 1));
-    const uint32_t ntaps = uint32_t(h - tf) / B + 1;
-    uint32_t idx = (sigma * (uint32_t(tf) - T)) & nmask;
-    Acc<R, KAHAN> acc;
-    int32_t t = tf;
-    for (uint32_t k0 = 0; k0 < ntaps; k0 += U) {
-      cplx<R> v[U];
-      R g[U];
-#pragma unroll
-      for (int r = 0; r < U; ++r) {
-        if (k0 + r < ntaps) {
-          v[r] = live ? Ld::load(xs, uint64_t(idx) * ld) : cplx<R>{0, 0};
-          g[r] = G[t < 0 ? -t : t];
-        } else {
-          v[r] = cplx<R>{0, 0};
-          g[r] = R(0);
-        }
-        idx = (idx + step) & nmask;
-        t += int32_t(B);
-      }
-#pragma unroll
-      for (int r = 0; r < U; ++r)
-        if (!KAHAN || k0 + r < ntaps) acc.add(g[r], v[r]);
-    }
-    cplx<R> out{acc.re, acc.im};
-    if (Ld::kScaled) out = cscale(out, scale);
-    tile[wave * kPerWave + q][lane] = out;
-  }
-  __syncthreads();
-  // each group of kIlvItems lanes writes one signal's run of items
-  for (uint32_t e = threadIdx.x; e < uint32_t(kIlvItems * kIlvSigs); e += 256) {
-    const uint32_t sl = e / kIlvItems, il = e % kIlvItems;
-    if (s0 + sl < nsig) ys[sl][tl.i0 + il] = tile[il][sl];
-  }
+  __shared__ IlvShared<typename Ld::R> sh;
+  fold_tile_ilv<Ld, KAHAN, U>(table, nsig, tiles[blockIdx.x], sh);
 }
 
 int fold_lds_bytes(int wg_per_cu) {

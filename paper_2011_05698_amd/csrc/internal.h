@@ -95,7 +95,8 @@ struct RoundItem {                 // one (signal, iteration, round)
 struct FftGroup {                  // round items [first, first + count), all with the same B
   uint32_t first, count;
 };
-constexpr uint32_t kFftGroupPoints = 2048;  // points one bucket-DFT workgroup takes when B is small
+constexpr uint32_t kFftGroupPoints = 2048;     // points one bucket-DFT workgroup takes when B is small (default)
+constexpr uint32_t kMaxFftGroupPoints = 4096;  // ... at most (the autotuner's choices)
 
 // ------------------------------------------------------------------ host --
 struct IterHost {
@@ -178,5 +179,33 @@ int launch_fold_interleaved(int dtype, int kahan, int unroll, const SignalDesc* 
 int launch_bucket_fft(int dtype, const SigArg& sig, const RoundItem* d_items, const FftGroup* d_groups,
                       uint32_t ngroups, uint32_t max_points, void* stream);
 int launch_recover(int dtype, const SigArg& sig, uint32_t nsig, void* stream);
+
+// LDS the recovery of one signal works in (with its few static arrays, two
+// workgroups fit a compute unit's 160 KiB).  The fused batch kernel uses the
+// same buffer for its fold tiles and bucket DFTs, so it takes plans whose
+// largest round (B_m complex values) fits in it.
+constexpr uint32_t kRecoverLdsBytes = 78848;
+
+// The batch as one persistent launch (fused.hip): work items in dependency
+// order.  kind kFusedFold: fold tile {grp, m, i0} (grp = signal, or signal
+// group of kIlvSigs in a position-major batch); kind kFusedFinish: bucket
+// DFTs and recovery of signal grp, after need[group] fold tiles of its group
+// are done.
+constexpr uint32_t kFusedFold = 0, kFusedFinish = 1;
+struct FusedItem {
+  uint32_t kind, grp, m, i0;
+};
+struct FusedArgs {
+  const SignalDesc* table;  // the batch's descriptor table
+  uint32_t nsig;
+  uint32_t nitems;
+  const FusedItem* items;
+  uint32_t* ctl;            // [0] queue head, [1] waits that gave up, [2 + g] fold tiles of group g done
+  const uint32_t* need;     // fold tiles of each group
+};
+// Zeroes ctl[0 .. nctl) with a small kernel, then launches the persistent
+// kernel with `grid` workgroups on `stream`.
+int launch_fused(int dtype, int kahan, bool position_major, uint32_t grid, uint32_t nctl, const FusedArgs& a,
+                 void* stream);
 
 }  // namespace sfft

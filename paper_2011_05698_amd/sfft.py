@@ -27,7 +27,7 @@ EXPORTED = [
     "sfft_default_options", "sfft_plan", "sfft_execute", "sfft_execute_noalloc", "sfft_hash_to_bins", "sfft_recover",
     "sfft_get_plan_info", "sfft_get_iter_info", "sfft_plan_dump_tables", "sfft_destroy",
     "sfft_batch_create", "sfft_execute_batch", "sfft_batch_launch_stage", "sfft_batch_destroy",
-    "sfft_batch_create_interleaved", "sfft_execute_interleaved", "sfft_plan_set_fold_config", "sfft_batch_set_fold_config", "sfft_batch_autotune", "sfft_status_string",
+    "sfft_batch_create_interleaved", "sfft_execute_interleaved", "sfft_plan_set_fold_config", "sfft_batch_set_fold_config", "sfft_batch_autotune", "sfft_batch_get_tuning", "sfft_batch_set_tuning", "sfft_status_string",
     "sfft_last_error",
 ]
 
@@ -47,6 +47,15 @@ class Options(ctypes.Structure):
 
 class FoldConfig(ctypes.Structure):
     _fields_ = [("unroll", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32), ("fold_ms", ctypes.c_double)]
+
+
+class BatchTuning(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("fused_chunk", ctypes.c_int32), ("fold_unroll", ctypes.c_int32),
+                ("fold_wg_per_cu", ctypes.c_int32), ("fft_group_points", ctypes.c_int32),
+                ("fused_available", ctypes.c_int32), ("step_ms", ctypes.c_double)]
+
+
+BATCH_MODES = {"stages": 0, "fused": 1}
 
 
 class PlanInfo(ctypes.Structure):
@@ -110,6 +119,8 @@ def _load():
         "sfft_plan_set_fold_config": (i32, [vp, ctypes.POINTER(FoldConfig)]),
         "sfft_batch_set_fold_config": (i32, [vp, ctypes.POINTER(FoldConfig)]),
         "sfft_batch_autotune": (i32, [vp, vp, ctypes.POINTER(FoldConfig)]),
+        "sfft_batch_get_tuning": (i32, [vp, ctypes.POINTER(BatchTuning)]),
+        "sfft_batch_set_tuning": (i32, [vp, ctypes.POINTER(BatchTuning)]),
         "sfft_batch_create_interleaved": (i32, [ctypes.POINTER(vp), vp, i32]),
         "sfft_execute_interleaved": (i32, [vp, vp, i64, vp, vp, vp, vp, vp]),
         "sfft_batch_destroy": (i32, [vp]),
@@ -245,6 +256,19 @@ def sfft_batch_autotune(batch, stream=None) -> dict:
     return {"unroll": c.unroll, "wg_per_cu": c.wg_per_cu, "fold_ms": c.fold_ms}
 
 
+def sfft_batch_get_tuning(batch) -> dict:
+    t = BatchTuning()
+    _check(_lib.sfft_batch_get_tuning(batch, ctypes.byref(t)))
+    return {"mode": {v: k for k, v in BATCH_MODES.items()}[t.mode], "fused_chunk": t.fused_chunk,
+            "fold_unroll": t.fold_unroll, "fold_wg_per_cu": t.fold_wg_per_cu, "fft_group_points": t.fft_group_points,
+            "fused_available": bool(t.fused_available), "step_ms": t.step_ms}
+
+
+def sfft_batch_set_tuning(batch, mode, fused_chunk, fold_unroll, fold_wg_per_cu, fft_group_points):
+    t = BatchTuning(BATCH_MODES[mode], fused_chunk, fold_unroll, fold_wg_per_cu, fft_group_points, 0, 0.0)
+    _check(_lib.sfft_batch_set_tuning(batch, ctypes.byref(t)))
+
+
 def sfft_batch_destroy(batch):
     _check(_lib.sfft_batch_destroy(batch))
 
@@ -365,6 +389,16 @@ class Batch:
         """Time the fold stage over its launch shapes and keep the fastest
         (needs buffers bound by a prior execute)."""
         return sfft_batch_autotune(self.handle, stream)
+
+    def tuning(self) -> dict:
+        return sfft_batch_get_tuning(self.handle)
+
+    def set_tuning(self, **kw):
+        """Changes some fields of the batch's tuning (see sfft_batch_tuning)."""
+        t = self.tuning()
+        t.update(kw)
+        sfft_batch_set_tuning(self.handle, t["mode"], t["fused_chunk"], t["fold_unroll"], t["fold_wg_per_cu"],
+                              t["fft_group_points"])
 
     def set_fold_config(self, unroll, wg_per_cu):
         sfft_batch_set_fold_config(self.handle, unroll, wg_per_cu)

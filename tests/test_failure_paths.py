@@ -80,9 +80,11 @@ def _sanitized_checker():
     """Builds the checker once per source state: plan.cpp and api.hip with
     host AddressSanitizer and UndefinedBehaviorSanitizer (device code of the
     kernel sources compiled as usual: only their host launchers are linked)."""
-    srcs = ["plan.cpp", "api.hip", "fold.hip", "bucket_fft.hip", "recover.hip"]
+    from paper_2011_05698_amd.build import SOURCES
+
+    srcs = list(SOURCES)
     h = hashlib.sha256()
-    for f in srcs + ["internal.h", "device_common.h"]:
+    for f in srcs + sorted(f for f in os.listdir(CSRC) if f.endswith(".h")):
         h.update(open(os.path.join(CSRC, f), "rb").read())
     h.update(open(os.path.join(INCLUDE, "sfft.h"), "rb").read())
     h.update(open(os.path.join(ROOT, "tests", "abi_host_check.cpp"), "rb").read())
