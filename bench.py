@@ -265,6 +265,8 @@ def main():
                     help="batch storage: sample c of signal s at X[c, s] (one plan), or one buffer per signal")
     ap.add_argument("--no-context", action="store_true", help="skip timing the other layout")
     ap.add_argument("--no-forms", action="store_true", help="skip the FP16 and uneven-batch context lines")
+    ap.add_argument("--large-oracle", type=int, default=0, metavar="SIGNALS",
+                    help="with --large-form: run the FP64 oracle on this many of its signals (about a minute each)")
     ap.add_argument("--large-form", type=int, default=0, metavar="SIGNALS",
                     help="also time the N=2^27, K=8192, B=16384 FP16 workload on this many signals")
     ap.add_argument("--fold-config", default=None, metavar="U,CAP",
@@ -342,12 +344,20 @@ def main():
         for _ in range(args.warmup):
             run()
         torch.cuda.synchronize()
-        # timed region: stage by stage, events between stages
+        tuning = batch.tuning()
+        fused = tuning["mode"] == "fused"
+        # timed region: the chosen configuration, launch by launch with events
+        # between the stages (the fused mode is one launch per step)
         ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for k in range(steps):
             ev[k][0].record(stream)
+            if fused:
+                batch.launch_stage(3)
+                for i in (1, 2, 3):
+                    ev[k][i].record(stream)
+                continue
             batch.launch_stage(0)
             ev[k][1].record(stream)
             batch.launch_stage(1)
@@ -366,7 +376,21 @@ def main():
         graph_ms = (time.perf_counter() - tg) * 1e3 / steps
         nsig = len(batch.plans)
         res = {"value": nsig * steps / elapsed, "ms_per_step": elapsed * 1e3 / steps,
-               "stage_ms": stage_ms, "graph_ms_per_step": graph_ms, "fold_cfg": fold_cfg}
+               "stage_ms": stage_ms, "graph_ms_per_step": graph_ms, "fold_cfg": fold_cfg, "tuning": tuning}
+        if tuning["fused_available"]:  # the other mode, for context
+            other = "stages" if fused else "fused"
+            batch.set_tuning(mode=other)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            fn = (lambda: [batch.launch_stage(i) for i in (0, 1, 2)]) if other == "stages" else (lambda: batch.launch_stage(3))
+            fn()
+            e0.record(stream)
+            for _ in range(3):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            res["other_mode"] = {"mode": other, "ms_per_step": round(e0.elapsed_time(e1) / 3, 4),
+                                 "fused_chunk": batch.tuning()["fused_chunk"]}
+            batch.set_tuning(mode=tuning["mode"])
         log(f"[{tag}] timed {steps} steps: {res['ms_per_step']:.3f} ms/step, {res['value']:.1f} signals/s; "
             f"stages ms {[round(v, 4) for v in stage_ms]}; graph {graph_ms:.3f} ms/step")
         return res
@@ -466,7 +490,7 @@ def main():
                              "recover": round(r["stage_ms"][2], 4)},
                 "graph_ms_per_step": round(r["graph_ms_per_step"], 4),
                 "fold_alg_gbs": round(alg / (r["stage_ms"][0] * 1e-3) / 1e9, 1),
-                "fold_launch": r["fold_cfg"]}
+                "fold_launch": r["fold_cfg"], "tuning": r["tuning"], "other_mode": r.get("other_mode")}
         return line, (xs_b, spec, outs_b)
 
     def large_form(nl, steps):
@@ -523,8 +547,52 @@ def main():
             common, a16, a32 = np.intersect1d(g16, g32, return_indices=True)
             agree.append(len(common) / max(len(g32), 1))
             worst = max(worst, float(np.linalg.norm(v16[a16] - v32[a32]) / max(np.linalg.norm(v32[a32]), 1e-300)))
+        # recall by magnitude decade: what the method finds of the planted
+        # coefficients of each size (log-uniform on [1e-2, 1])
+        by_mag = {}
+        for lo, hi in ((1e-2, 1e-1), (1e-1, 1.0)):
+            hit = tot = 0
+            for i in range(nl):
+                sup, vals = planted_spectrum(NL, KL, 501 + i, mags="loguniform")
+                sel = sup[(np.abs(vals) >= lo) & (np.abs(vals) < hi)]
+                c16 = int(o16[2][i].item())
+                hit += len(np.intersect1d(o16[0][i, :c16].cpu().numpy(), sel))
+                tot += len(sel)
+            by_mag[f"[{lo:g}, {hi:g})"] = round(hit / max(tot, 1), 4)
+        oracle_cmp = None
+        if args.large_oracle:
+            from fractions import Fraction
+
+            from oracle import sfft_oracle as O
+
+            PL = O.make_plan(NL, KL, BL, wl, ML, l, Fraction(q), delta, seed=502)
+            oracle_cmp = []
+            for i in range(min(args.large_oracle, nl)):
+                row = {"signal": i}
+                h = X16[:, i].float().cpu().numpy().astype(np.float64)
+                for tag, xin, outs_ in (("f16", (h[:, 0] + 1j * h[:, 1]) * sc[i], o16),
+                                        ("f32", X32[:, i].cpu().numpy().astype(np.complex128), o32)):
+                    t1 = time.perf_counter()
+                    oi, ov, _ = O.sfft(xin, PL)
+                    c = int(outs_[2][i].item())
+                    gi = outs_[0][i, :c].cpu().numpy()
+                    gv = outs_[1][i, :c].cpu().numpy().astype(np.complex128)
+                    common, ga, oa = np.intersect1d(gi, oi, return_indices=True)
+                    pc = np.abs(gv[ga] - ov[oa]) / np.maximum(np.abs(ov[oa]), 1e-300)
+                    row[tag] = {"oracle_s": round(time.perf_counter() - t1, 1), "gpu_count": c, "oracle_count": len(oi),
+                                "support_identical": bool(np.array_equal(gi, oi)),
+                                "support_agreement": round(len(common) / max(len(oi), len(gi), 1), 5),
+                                "rel_l2_common": float(np.linalg.norm(gv[ga] - ov[oa]) /
+                                                       max(np.linalg.norm(ov[oa]), 1e-300)),
+                                "per_coefficient_rel_err": {"max": float(pc.max()) if len(pc) else 0.0,
+                                                            "p99": float(np.quantile(pc, 0.99)) if len(pc) else 0.0,
+                                                            "median": float(np.median(pc)) if len(pc) else 0.0}}
+                    log(f"[large {tag}] oracle on signal {i}: {row[tag]}")
+                oracle_cmp.append(row)
+                del h
         alg = nl * (p16.samples * 4 + p16.yhat_elems * 8)
         return {"N": NL, "K": KL, "B": BL, "w": wl, "loops": ML, "signals": nl, "snr_db": 40,
+                "recall_f16_by_magnitude": by_mag, "oracle": oracle_cmp,
                 "mags": "log-uniform [1e-2, 1]", "storage": "f16 pairs + per-signal f32 scale",
                 "signals_per_s": round(r["value"], 2), "ms_per_step": round(r["ms_per_step"], 3),
                 "stage_ms": {"fold": round(r["stage_ms"][0], 4), "bucket_fft": round(r["stage_ms"][1], 4),
@@ -679,9 +747,12 @@ def main():
     lay = "posmajor" if args.layout == "position-major" else "persignal"
     tag = f"metric_batch{n}_{dt}_{lay}" if (N, K, B, M, args.snr) == (2 ** 22, 1000, 2048, 12, None) else None
     traffic, source = measured_traffic(tag) if tag else (None, None)
+    fold_kernel = "fold_interleaved_kernel" if args.layout == "position-major" else "fold_kernel"
+    if main_res["tuning"]["mode"] == "fused":  # one kernel per step: price the whole step's gathers on it
+        fold_kernel, traffic, source = "fused_kernel", None, "the fused launch: counters not taken"
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-                "kernel": "fold_interleaved_kernel" if args.layout == "position-major" else "fold_kernel",
+                "kernel": fold_kernel,
                 "alg_bytes_per_launch": alg_bytes,
                 "avg_launch_ms": round(stage_ms[0], 5)}
     if traffic:
@@ -843,6 +914,7 @@ def main():
                 ("bucket_fft", "lds", n * plan.yhat_elems * (16 if dt == "c128" else 8) * 2, stage_ms[1]),
                 ("recover", "latency", n * plan.yhat_elems * (16 if dt == "c128" else 8), stage_ms[2]))},
         "fold_launch": fold_cfg,
+        "tuning": main_res["tuning"], "other_mode": main_res.get("other_mode"),
         "other_layout": context,
         "forms": forms or None,
     }
