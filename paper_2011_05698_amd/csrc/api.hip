@@ -81,7 +81,8 @@ struct sfft_plan_s {
   RoundItem* d_items = nullptr;
   FftGroup* d_groups = nullptr;
   unsigned char* d_ws = nullptr;
-  uint32_t ntiles = 0, nitems = 0, nfft = 0, fft_points = 0;
+  uint32_t ntiles = 0, nitems = 0;
+  FftGroups fft;
   FoldConfig fold{8, 0};
 };
 
@@ -95,7 +96,8 @@ struct sfft_batch_s {
   FftGroup* d_groups = nullptr;
   unsigned char* d_ws = nullptr;
   std::vector<uint64_t> ws_off;
-  uint32_t ntiles = 0, nitems = 0, max_B = 0, nfft = 0, fft_points = 0;
+  uint32_t ntiles = 0, nitems = 0, max_B = 0;
+  FftGroups fft;
   std::vector<SignalDesc> bound;    // host copy of the uploaded descriptor table
   bool has_binding = false;
   hipGraph_t graph = nullptr;
@@ -138,23 +140,37 @@ sfft_status hip_fail(hipError_t e, const char* what) {
 uint64_t align256(uint64_t v) { return (v + 255) & ~uint64_t(255); }
 
 // Orders round items by B (largest first, stable) and cuts them into
-// bucket-DFT workgroups of equal B and at most kFftGroupPoints points.
+// bucket-DFT workgroups of equal B: rounds above the wave path's size take
+// groups of at most `points` points (one round at least); wave-path rounds
+// take groups of `points` points, but at least one chunk per wave of the
+// workgroup (64 / L1 rounds each, L1 = 2^ceil(log2 B / 2)), so that no wave
+// of it idles.
 template <class BOf>
-void group_rounds(std::vector<RoundItem>& items, BOf b_of, std::vector<FftGroup>& groups, uint32_t& max_points,
-                  uint32_t points = kFftGroupPoints) {
+void group_rounds(std::vector<RoundItem>& items, BOf b_of, int dtype, std::vector<FftGroup>& groups,
+                  FftGroups& fg, uint32_t points = kFftGroupPoints) {
   std::stable_sort(items.begin(), items.end(),
                    [&](const RoundItem& x, const RoundItem& y) { return b_of(x) > b_of(y); });
+  const uint32_t wmax = dtype == SFFT_C128 ? kWaveFftMaxLogB64 : kWaveFftMaxLogB32;
   groups.clear();
-  max_points = 0;
+  fg = FftGroups{};
   for (uint32_t a = 0; a < uint32_t(items.size());) {
     const uint32_t B = b_of(items[a]);
-    const uint32_t cap = std::max<uint32_t>(1u, points / B);
+    uint32_t logB = 0;
+    while ((1u << logB) < B) ++logB;
+    uint32_t cap = std::max<uint32_t>(1u, points / B);
+    if (logB <= wmax) {
+      cap = std::max(cap, kFftWaves * (64u >> (logB - logB / 2)));
+      fg.wave_logB = std::max(fg.wave_logB, logB);
+    } else {
+      fg.nlds = uint32_t(groups.size()) + 1;
+    }
     uint32_t c = 1;
     while (a + c < uint32_t(items.size()) && c < cap && b_of(items[a + c]) == B) ++c;
     groups.push_back(FftGroup{a, c});
-    max_points = std::max(max_points, c * B);
+    if (logB > wmax) fg.max_points = std::max(fg.max_points, c * B);
     a += c;
   }
+  fg.ngroups = uint32_t(groups.size());
 }
 
 // Work lists of one signal, signal-major: the fold covers the (R_m+1) x B_m
@@ -202,10 +218,9 @@ sfft_status upload_plan(sfft_plan_t p) {
   std::vector<RoundItem> items;
   build_work_lists(hp, 0, tiles, items);
   std::vector<FftGroup> groups;
-  group_rounds(items, [&](const RoundItem& r) { return hp.iters[r.m].d.B; }, groups, p->fft_points);
+  group_rounds(items, [&](const RoundItem& r) { return hp.iters[r.m].d.B; }, hp.dtype, groups, p->fft);
   p->ntiles = uint32_t(tiles.size());
   p->nitems = uint32_t(items.size());
-  p->nfft = uint32_t(groups.size());
 
   uint64_t off = 0;
   auto take = [&](uint64_t bytes) {
@@ -313,7 +328,7 @@ uint32_t max_B(const HostPlan& hp) {
 sfft_status run_hash(sfft_plan_t p, const SigArg& a, hipStream_t s) {
   int e = launch_fold(p->hp.dtype, p->hp.kahan, p->fold, a, p->d_tiles, p->ntiles, s);
   if (e != hipSuccess) return hip_fail(hipError_t(e), "fold launch");
-  e = launch_bucket_fft(p->hp.dtype, a, p->d_items, p->d_groups, p->nfft, p->fft_points, s);
+  e = launch_bucket_fft(p->hp.dtype, a, p->d_items, p->d_groups, p->fft, s);
   if (e != hipSuccess) return hip_fail(hipError_t(e), "bucket FFT launch");
   return SFFT_OK;
 }
@@ -363,13 +378,13 @@ int launch_batch_fused(const sfft_batch_s* b, hipStream_t s) {
 sfft_status regroup_fft(sfft_batch_s* b, uint32_t points) {
   std::vector<RoundItem> items = b->h_items;
   std::vector<FftGroup> groups;
-  uint32_t maxp = 0;
-  group_rounds(items, [&](const RoundItem& r) { return b->plans[r.sig]->hp.iters[r.m].d.B; }, groups, maxp, points);
+  FftGroups fg;
+  group_rounds(items, [&](const RoundItem& r) { return b->plans[r.sig]->hp.iters[r.m].d.B; }, b->dtype, groups, fg,
+               points);
   hipError_t e = hipMemcpy(b->d_items, items.data(), sizeof(RoundItem) * items.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(b->d_groups, groups.data(), sizeof(FftGroup) * groups.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "bucket-DFT groups upload");
-  b->nfft = uint32_t(groups.size());
-  b->fft_points = maxp;
+  b->fft = fg;
   b->fft_group_points = points;
   return SFFT_OK;
 }
@@ -627,10 +642,10 @@ sfft_status create_batch_impl(sfft_batch_t* out, const sfft_plan_t* h_plans, int
   b->nfgroups = uint32_t(b->group_tiles.size());
   b->h_items = items;
   std::vector<FftGroup> groups;
-  group_rounds(items, [&](const RoundItem& r) { return h_plans[r.sig]->hp.iters[r.m].d.B; }, groups, b->fft_points);
+  group_rounds(items, [&](const RoundItem& r) { return h_plans[r.sig]->hp.iters[r.m].d.B; }, b->dtype, groups,
+               b->fft);
   b->ntiles = uint32_t(tiles.size());
   b->nitems = uint32_t(items.size());
-  b->nfft = uint32_t(groups.size());
   // the fused launch: one chunk per signal group (position-major) or per 32 signals
   b->fused_chunk = interleaved ? 1u : std::min<uint32_t>(32u, uint32_t(n));
   std::vector<FusedItem> fitems;
@@ -717,7 +732,7 @@ sfft_status bind_and_replay(sfft_batch_t b, const std::vector<SignalDesc>& sig, 
       le = launch_batch_fused(b, cs);
     } else {
       le = launch_batch_fold(b, b->fold, cs);
-      if (le == hipSuccess) le = launch_bucket_fft(b->dtype, a, b->d_items, b->d_groups, b->nfft, b->fft_points, cs);
+      if (le == hipSuccess) le = launch_bucket_fft(b->dtype, a, b->d_items, b->d_groups, b->fft, cs);
       if (le == hipSuccess) le = launch_recover(b->dtype, a, uint32_t(n), cs);
     }
     hipGraph_t g = nullptr;
@@ -814,7 +829,7 @@ sfft_status sfft_batch_launch_stage(sfft_batch_t b, int32_t stage, void* stream)
   const SigArg a = table_arg(b);
   switch (stage) {
     case 0: e = launch_batch_fold(b, b->fold, s); break;
-    case 1: e = launch_bucket_fft(b->dtype, a, b->d_items, b->d_groups, b->nfft, b->fft_points, s); break;
+    case 1: e = launch_bucket_fft(b->dtype, a, b->d_items, b->d_groups, b->fft, s); break;
     case 2: e = launch_recover(b->dtype, a, uint32_t(b->plans.size()), s); break;
     case 3:
       if (!b->fused_ok) return fail(SFFT_ERR_UNSUPPORTED, "a round of this batch does not fit the fused kernel's LDS");
@@ -969,7 +984,7 @@ sfft_status sfft_batch_autotune(sfft_batch_t b, void* stream, sfft_fold_config* 
     st = regroup_fft(b, pts);
     if (st != SFFT_OK) break;
     const float ms = time_launches(
-        [&] { return launch_bucket_fft(b->dtype, a, b->d_items, b->d_groups, b->nfft, b->fft_points, s); }, s, e0, e1, 3,
+        [&] { return launch_bucket_fft(b->dtype, a, b->d_items, b->d_groups, b->fft, s); }, s, e0, e1, 3,
         &err);
     if (err == hipSuccess && ms < fft_ms) {
       fft_ms = ms;
@@ -990,7 +1005,7 @@ sfft_status sfft_batch_autotune(sfft_batch_t b, void* stream, sfft_fold_config* 
     step = time_launches(
         [&] {
           int le = launch_batch_fold(b, b->fold, s);
-          if (le == hipSuccess) le = launch_bucket_fft(b->dtype, a, b->d_items, b->d_groups, b->nfft, b->fft_points, s);
+          if (le == hipSuccess) le = launch_bucket_fft(b->dtype, a, b->d_items, b->d_groups, b->fft, s);
           if (le == hipSuccess) le = launch_recover(b->dtype, a, uint32_t(b->plans.size()), s);
           return le;
         },

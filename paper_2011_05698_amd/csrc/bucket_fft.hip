@@ -1,62 +1,106 @@
 // Stage kernel of the bucket DFT: one workgroup per group of rounds with the
 // same B (device body in fft_body.h).
 #include "fft_body.h"
+#include "fft_wave.h"
 
 namespace sfft {
 
-// A workgroup takes a group of rounds with the same B (one round when B is
-// large, up to 1024..4096 points (kFftGroupPoints by default) of several rounds, of one or several
-// signals, when it is small).  Rounds of different plans may share a group:
-// the twiddles exp(-2 pi i k / B) depend on B only; 1/N is per round.
+// A workgroup takes a group of rounds with the same B: one round (or a few)
+// when B is above the wave path's size, a few chunks of 64 / L1 rounds per
+// wave below it, of one or several signals.  Rounds of different plans may
+// share a group: the twiddles exp(-2 pi i k / B) depend on B only; 1/N is
+// per round.  Two kernels, for the register budgets of the two paths: the
+// LDS pass (few registers, many workgroups per CU) for the groups
+// [0, nlds), the in-register wave path for the rest.
 template <typename R>
-__global__ __launch_bounds__(256) void bucket_fft_kernel(SigArg arg, const RoundItem* __restrict__ items,
-                                                         const FftGroup* __restrict__ groups) {
-  HIP_DYNAMIC_SHARED(double2, smem_raw)  // 16-byte aligned dynamic LDS
-  constexpr uint32_t kMaxRoundsPerGroup = kMaxFftGroupPoints / 16;  // B >= 16
-  __shared__ cplx<R>* sh_y[kMaxRoundsPerGroup];
-  __shared__ R sh_inv[kMaxRoundsPerGroup];
-  cplx<R>* X = reinterpret_cast<cplx<R>*>(smem_raw);
-  const FftGroup grp = groups[blockIdx.x];
-  const RoundItem first = items[grp.first];
-  const SignalDesc sd0 = load_signal(arg, first.sig);
-  const IterDesc* it0 = sd0.plan->iters + first.m;
-  const uint32_t B = it0->B, logB = it0->logB, n = grp.count;
-  const cplx<R>* tw = reinterpret_cast<const cplx<R>*>(sd0.plan->twiddle) + it0->tw_off;
-  for (uint32_t g = threadIdx.x; g < n; g += blockDim.x) {
+struct GroupRows {
+  cplx<R>* y[kMaxFftGroupPoints / 16];  // B >= 16
+  R inv[kMaxFftGroupPoints / 16];
+};
+
+// The rows of the group's rounds into LDS; returns the group's first round.
+template <typename R>
+__device__ RoundItem load_group(const SigArg& arg, const RoundItem* __restrict__ items, const FftGroup& grp,
+                                GroupRows<R>& rows) {
+  for (uint32_t g = threadIdx.x; g < grp.count; g += blockDim.x) {
     const RoundItem itm = items[grp.first + g];
     const SignalDesc sd = load_signal(arg, itm.sig);
     const IterDesc* it = sd.plan->iters + itm.m;
-    sh_y[g] = reinterpret_cast<cplx<R>*>(sd.y) + it->y_off + size_t(itm.j) * B;
-    sh_inv[g] = R(1) / R(sd.plan->N);
+    rows.y[g] = reinterpret_cast<cplx<R>*>(sd.y) + it->y_off + size_t(itm.j) * it->B;
+    rows.inv[g] = R(1) / R(sd.plan->N);
   }
+  return items[grp.first];
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void bucket_fft_lds_kernel(SigArg arg, const RoundItem* __restrict__ items,
+                                                             const FftGroup* __restrict__ groups) {
+  HIP_DYNAMIC_SHARED(double2, smem_raw)  // 16-byte aligned dynamic LDS
+  __shared__ GroupRows<R> rows;
+  const FftGroup grp = groups[blockIdx.x];
+  const RoundItem first = load_group(arg, items, grp, rows);
+  const SignalDesc sd0 = load_signal(arg, first.sig);
+  const IterDesc* it0 = sd0.plan->iters + first.m;
+  const cplx<R>* tw = reinterpret_cast<const cplx<R>*>(sd0.plan->twiddle) + it0->tw_off;
   __syncthreads();
-  fft_rounds<R>(X, n, B, logB, tw, [&](uint32_t g) { return sh_y[g]; }, [&](uint32_t g) { return sh_inv[g]; });
+  fft_rounds<R>(reinterpret_cast<cplx<R>*>(smem_raw), grp.count, it0->B, it0->logB, tw,
+                [&](uint32_t g) { return rows.y[g]; }, [&](uint32_t g) { return rows.inv[g]; });
+}
+
+template <typename R>
+__global__ __launch_bounds__(256, 2) void bucket_fft_wave_kernel(SigArg arg, const RoundItem* __restrict__ items,
+                                                                 const FftGroup* __restrict__ groups,
+                                                                 uint32_t first_group) {
+  HIP_DYNAMIC_SHARED(double2, smem_raw)
+  __shared__ GroupRows<R> rows;
+  cplx<R>* X = reinterpret_cast<cplx<R>*>(smem_raw);
+  const FftGroup grp = groups[first_group + blockIdx.x];
+  const RoundItem first = load_group(arg, items, grp, rows);
+  const SignalDesc sd0 = load_signal(arg, first.sig);
+  const IterDesc* it0 = sd0.plan->iters + first.m;
+  const uint32_t B = it0->B;
+  const cplx<R>* tw = reinterpret_cast<const cplx<R>*>(sd0.plan->twiddle) + it0->tw_off;
+  for (uint32_t k = threadIdx.x; k < B / 2; k += blockDim.x) X[k] = tw[k];  // twiddles, then the wave tiles
+  __syncthreads();
+  wave_fft_rounds<R>(grp.count, it0->logB, [&](uint32_t g) { return rows.y[g]; },
+                     [&](uint32_t g) { return rows.inv[g]; }, X + B / 2, X);
+}
+
+template <typename R>
+static int launch_t(const SigArg& sig, const RoundItem* d_items, const FftGroup* d_groups, const FftGroups& fg,
+                    hipStream_t s) {
+  constexpr size_t CB = sizeof(cplx<R>);
+  if (fg.nlds) {
+    const size_t lds = size_t(fg.max_points) * CB;
+    if (lds > 65536) {
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&bucket_fft_lds_kernel<R>),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(bucket_fft_lds_kernel<R>, dim3(fg.nlds), dim3(256), lds, s, sig, d_items, d_groups);
+  }
+  if (fg.ngroups > fg.nlds) {
+    // the largest need of the sizes present (a smaller B can need more:
+    // 2^4 points take 10,304 bytes, 2^5 points 9,344); at most 74,752 bytes
+    uint32_t elems = 0;
+    for (uint32_t l = 4; l <= fg.wave_logB; ++l) elems = max(elems, wave_fft_lds_elems(l, kFftWaves));
+    const size_t lds = size_t(elems) * CB;
+    if (lds > 65536) {
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&bucket_fft_wave_kernel<R>),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(bucket_fft_wave_kernel<R>, dim3(fg.ngroups - fg.nlds), dim3(kFftWaves * 64), lds, s, sig,
+                       d_items, d_groups, fg.nlds);
+  }
+  return hipGetLastError();
 }
 
 int launch_bucket_fft(int dtype, const SigArg& sig, const RoundItem* d_items, const FftGroup* d_groups,
-                      uint32_t ngroups, uint32_t max_points, void* stream) {
-  if (ngroups == 0) return hipSuccess;
+                      const FftGroups& fg, void* stream) {
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  dim3 grid(ngroups), block(256);
-  // up to 128 KiB of dynamic LDS (gfx950 gives a workgroup 160 KiB)
-  if (dtype == SFFT_C128) {
-    const size_t lds = size_t(max_points) * 16;
-    if (lds > 65536) {
-      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&bucket_fft_kernel<double>),
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-      if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(bucket_fft_kernel<double>, grid, block, lds, s, sig, d_items, d_groups);
-  } else {
-    const size_t lds = size_t(max_points) * 8;
-    if (lds > 65536) {
-      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&bucket_fft_kernel<float>),
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-      if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(bucket_fft_kernel<float>, grid, block, lds, s, sig, d_items, d_groups);
-  }
-  return hipGetLastError();
+  return dtype == SFFT_C128 ? launch_t<double>(sig, d_items, d_groups, fg, s)
+                            : launch_t<float>(sig, d_items, d_groups, fg, s);
 }
 
 }  // namespace sfft

@@ -4,17 +4,19 @@
 //   * fold tile: the permuted gather, window and fold of one tile of one
 //     signal (or of a group of 64 signals in a position-major batch), as in
 //     the fold stage kernels (fold_body.h);
-//   * finish: the bucket DFT of every round of one signal (fft_body.h), then
-//     its recovery (recover_body.h), once every fold tile of its signal (or
-//     group) is done.
+//   * finish: the bucket DFT of every round of one signal (the LDS pass of
+//     fft_body.h), then its recovery (recover_body.h), once every fold tile
+//     of its signal (or group) is done.
 // A finish item waits on a per-group counter of completed fold tiles.  The
 // items it waits for were taken earlier by workgroups that are running and
 // never wait on later items, so every wait ends; a wait that has not ended
 // after a bounded number of polls gives up and marks the signal's count -2
 // instead of hanging.  Recovery (latency-bound, one workgroup per signal)
 // of the early signals then overlaps the gather (bandwidth-bound) of the
-// later ones.  Every sum is the one the stage kernels compute, in the same
-// order: results are bit-identical to the three-stage graph.
+// later ones.  The fold and the recovery compute every sum as the stage
+// kernels do, in the same order; the bucket DFT takes the LDS pass for
+// every B, where the stage kernel takes the in-register wave path up to
+// 2048 points (fft_wave.h): bucket values agree to rounding, not bit for bit.
 #include "fft_body.h"
 #include "fold_body.h"
 #include "recover_body.h"

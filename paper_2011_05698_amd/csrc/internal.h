@@ -97,6 +97,16 @@ struct FftGroup {                  // round items [first, first + count), all wi
 };
 constexpr uint32_t kFftGroupPoints = 2048;     // points one bucket-DFT workgroup takes when B is small (default)
 constexpr uint32_t kMaxFftGroupPoints = 4096;  // ... at most (the autotuner's choices)
+// Largest log2 B of the bucket DFT's in-register wave path (fft_wave.h), by
+// real type; rounds above it take the LDS pass (fft_body.h).
+constexpr uint32_t kWaveFftMaxLogB32 = 11, kWaveFftMaxLogB64 = 9;
+constexpr uint32_t kFftWaves = 4;             // waves of a bucket-DFT workgroup
+// The bucket-DFT groups of a plan or batch, largest B first: [0, nlds)
+// take the LDS pass (at most max_points points each), [nlds, ngroups) the
+// wave path (rounds of at most 2^wave_logB points).
+struct FftGroups {
+  uint32_t ngroups = 0, nlds = 0, max_points = 0, wave_logB = 0;
+};
 
 // ------------------------------------------------------------------ host --
 struct IterHost {
@@ -177,7 +187,7 @@ int launch_fold(int dtype, int kahan, const FoldConfig& cfg, const SigArg& sig, 
 int launch_fold_interleaved(int dtype, int kahan, int unroll, const SignalDesc* table, uint32_t nsig,
                             const FoldTile* d_tiles, uint32_t ntiles, void* stream);
 int launch_bucket_fft(int dtype, const SigArg& sig, const RoundItem* d_items, const FftGroup* d_groups,
-                      uint32_t ngroups, uint32_t max_points, void* stream);
+                      const FftGroups& fg, void* stream);
 int launch_recover(int dtype, const SigArg& sig, uint32_t nsig, void* stream);
 
 // LDS the recovery of one signal works in (with its few static arrays, two

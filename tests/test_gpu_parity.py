@@ -70,6 +70,28 @@ def values_ok(gidx, gval, oidx, oval, tol):
     return err, pmax
 
 
+def rounding_close(gidx, gval, sidx, sval, flips=0, tol=1e-3):
+    """A result of the fused launch against the stage launches' result for
+    the same input: the fused kernel takes the bucket DFT's LDS pass where
+    the stage kernel takes the in-register wave path, so bucket values agree
+    to rounding only.  Supports agree up to `flips` frequencies (decisions
+    within rounding of their thresholds), and the values of the common
+    support within tol (rel-L2): a per-loop decision within rounding of its
+    threshold (a verification, a direct position at a half-integer) changes
+    which loop estimates a median takes, which moves it by their spread
+    (input quantization noise in FP16 storage), not by a rounding error.
+    Each path is checked against the oracle at the value tolerance (1e-4 in
+    FP32, 1e-10 in FP64) besides."""
+    diff = set(int(f) for f in gidx) ^ set(int(f) for f in sidx)
+    assert len(diff) <= flips, diff
+    common, gi, si = np.intersect1d(gidx, sidx, return_indices=True)
+    a = np.asarray(gval, dtype=np.complex128)[gi]
+    b = np.asarray(sval, dtype=np.complex128)[si]
+    err = rel_l2(a, b) if len(common) else 0.0
+    assert err <= tol, err
+    return err
+
+
 def noisy_ok(gidx, gval, oidx, oval, info, P, common_frac, tol):
     """Noisy inputs: supports agree on at least common_frac, every mismatch is
     a near-tie, and the common values agree within tol (rel-L2)."""
@@ -400,9 +422,9 @@ def test_batch_uneven_matches_single(sf):
             assert np.array_equal(gi, singles[s][0])
             assert np.array_equal(gv, singles[s][1].astype(np.complex64))
             values_ok(gi, gv, oracles[s][0], oracles[s][1], 1e-4)
-    # every fold launch shape sums the taps of a bucket in the same order, and
-    # the fused persistent launch runs the same arithmetic, so the tuned and
-    # the explicitly chosen configurations give bit-identical results
+    # every fold launch shape sums the taps of a bucket in the same order, so
+    # the stage configurations give bit-identical results; the fused launch
+    # agrees to rounding (its bucket DFT is the LDS pass)
     best = batch.autotune()
     assert best["unroll"] in (8, 16, 24) and best["fold_ms"] > 0
     t = batch.tuning()
@@ -416,9 +438,16 @@ def test_batch_uneven_matches_single(sf):
             torch.cuda.synchronize()
             for s in range(len(specs)):
                 c = int(counts[s].item())
+                gi = idxs[s][:c].cpu().numpy()
+                gv = vals[s][:c].cpu().numpy()
+                if cfg["mode"] == "fused":
+                    rounding_close(gi, gv, singles[s][0], singles[s][1])
+                    values_ok(gi, gv, oracles[s][0], oracles[s][1], 1e-4)
+                    continue
                 assert c == singles[s][2], (cfg, s, c)
-                assert np.array_equal(idxs[s][:c].cpu().numpy(), singles[s][0])
-                assert np.array_equal(vals[s][:c].cpu().numpy(), singles[s][1].astype(np.complex64))
+                assert np.array_equal(gi, singles[s][0]), (cfg, s)
+                sv = singles[s][1].astype(np.complex64)
+                assert np.array_equal(gv, sv), (cfg, s, float(np.max(np.abs(gv - sv))))
     with pytest.raises(sf.SfftError):
         batch.set_fold_config(12, 0)
 
@@ -472,26 +501,33 @@ def _check_position_major(sf, dtype, kahan, nsig, ld, location="multiscale", com
         singles.append(run_gpu(sf, plan, xd, scale))
     X = _position_major(xs, ld, dtype)
     batch = sf.InterleavedBatch(plan, nsig)
-    # the three stage launches at two fold shapes, then the fused persistent
-    # launch at two chunk sizes: every configuration gives the same bits
+    # the three stage launches at two fold shapes give the same bits; the
+    # fused persistent launch at two chunk sizes agrees to rounding
     configs = [dict(mode="stages", fold_unroll=8), dict(mode="stages", fold_unroll=24, fft_group_points=1024),
                dict(mode="fused", fused_chunk=1), dict(mode="fused", fused_chunk=(nsig + 63) // 64)]
+    last = {}
     for cfg in configs:
         batch.set_tuning(**cfg)
         for _ in range(2):  # a second replay of the same graph
             idx, val, cnt = batch.execute(X, scales=scales)
             torch.cuda.synchronize()
+            last[cfg["mode"]] = (idx.clone(), val.clone(), cnt.clone())
             for s in range(nsig):
                 c = int(cnt[s].item())
+                if cfg["mode"] == "fused":
+                    rounding_close(idx[s, :c].cpu().numpy(), val[s, :c].cpu().numpy(), singles[s][0],
+                                   singles[s][1], tol=1e-9 if dtype == "c128" else 1e-3)
+                    continue
                 assert c == singles[s][2], (cfg, s, c)
                 assert np.array_equal(idx[s, :c].cpu().numpy(), singles[s][0])
                 assert np.array_equal(val[s, :c].cpu().numpy(), singles[s][1])
-    for s in (0, nsig - 1):
+    for s in (0, nsig - 1):  # both launch forms against the oracle
         oidx, oval, _ = O.sfft(xqs[s], O.make_plan(N, K, B, w, M, 16, 1, 1e-6, seed=900, location=location,
                                                    combine=combine))
-        c = int(cnt[s].item())
-        values_ok(idx[s, :c].cpu().numpy(), val[s, :c].cpu().numpy(), oidx, oval,
-                  1e-10 if dtype == "c128" else 1e-4)
+        for idx_, val_, cnt_ in last.values():
+            c = int(cnt_[s].item())
+            values_ok(idx_[s, :c].cpu().numpy(), val_[s, :c].cpu().numpy(), oidx, oval,
+                      1e-10 if dtype == "c128" else 1e-4)
     with pytest.raises(sf.SfftError):
         sf.sfft_execute_interleaved(batch.handle, X, nsig - 1, scales, idx, val, cnt)
 
@@ -518,10 +554,15 @@ def test_position_major_metric_shape(sf):
     for cfg in (None, dict(mode="stages"), dict(mode="fused", fused_chunk=1)):
         if cfg:
             batch.set_tuning(**cfg)
+        fused = batch.tuning()["mode"] == "fused"
         idx, val, cnt = batch.execute(X)
         torch.cuda.synchronize()
         for s in range(nsig):
             gi, gv, c = singles[s]
+            if fused:  # decisions within rounding of a threshold may flip: a few of K = 1000
+                rounding_close(idx[s, :int(cnt[s].item())].cpu().numpy(), val[s, :int(cnt[s].item())].cpu().numpy(),
+                               gi, gv, flips=5)
+                continue
             assert int(cnt[s].item()) == c, (cfg, s)
             assert np.array_equal(idx[s, :c].cpu().numpy(), gi)
             assert np.array_equal(val[s, :c].cpu().numpy(), gv)
