@@ -902,16 +902,17 @@ def main():
                      "recover": round(stage_ms[2], 4)},
         "graph_ms_per_step": round(graph_ms, 4),
         # the two other stages against HBM: bucket values read and written once
-        # by the bucket DFT, read once by the recovery (its store, hash index
-        # and outputs are smaller).  Neither is bound by HBM: the DFT by LDS
-        # and barriers, the recovery by dependent latency (one workgroup per
-        # signal, iterations in order).
+        # by the bucket DFT, read once by the recovery (its store and outputs
+        # are smaller).  Neither reaches the HBM peak: the DFT is bound by the
+        # load latency of its waves (load, in-register DFTs, store in sequence
+        # at two waves per SIMD), the recovery by dependent latency (one
+        # workgroup per signal, iterations in order).
         "stage_roofline": {
             st: {"bound": bound, "alg_bytes_per_launch": nb,
                  "achieved_gbs": round(nb / (ms * 1e-3) / 1e9, 1),
                  "frac_of_hbm_peak": round(nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
             for st, bound, nb, ms in (
-                ("bucket_fft", "lds", n * plan.yhat_elems * (16 if dt == "c128" else 8) * 2, stage_ms[1]),
+                ("bucket_fft", "latency", n * plan.yhat_elems * (16 if dt == "c128" else 8) * 2, stage_ms[1]),
                 ("recover", "latency", n * plan.yhat_elems * (16 if dt == "c128" else 8), stage_ms[2]))},
         "fold_launch": fold_cfg,
         "tuning": main_res["tuning"], "other_mode": main_res.get("other_mode"),

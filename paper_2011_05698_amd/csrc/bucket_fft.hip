@@ -80,8 +80,9 @@ static int launch_t(const SigArg& sig, const RoundItem* d_items, const FftGroup*
     hipLaunchKernelGGL(bucket_fft_lds_kernel<R>, dim3(fg.nlds), dim3(256), lds, s, sig, d_items, d_groups);
   }
   if (fg.ngroups > fg.nlds) {
-    // the largest need of the sizes present (a smaller B can need more:
-    // 2^4 points take 10,304 bytes, 2^5 points 9,344); at most 74,752 bytes
+    // the largest need of the sizes up to the largest present (a smaller B
+    // can need more: 2^6 points take 18,688 bytes of complex64, 2^7 points
+    // 18,944, 2^4 points 10,304 and 2^5 points 10,368); at most 75,776 bytes
     uint32_t elems = 0;
     for (uint32_t l = 4; l <= fg.wave_logB; ++l) elems = max(elems, wave_fft_lds_elems(l, kFftWaves));
     const size_t lds = size_t(elems) * CB;

@@ -8,7 +8,8 @@
 //           takes their R1-point DFT in registers (radix 2, unrolled);
 //           then the twiddle W_B^{n2 k1};
 //   LDS:    the R1 x L1 results go through a padded LDS tile of the wave
-//           (row stride L1 + 1: no two lanes of a read share a bank);
+//           (row stride L1 + 1, or L1 + 2 when L1 = 2 R1, so that the lanes
+//           of a read do not share banks);
 //   pass 2: each k1 takes the L1-point DFT over n2: when L1 = R1 one lane
 //           does it in registers; when L1 = 2 R1 two neighbouring lanes
 //           each do the R1-point DFT of the even or the odd n2, and a DPP
@@ -146,10 +147,18 @@ __device__ __forceinline__ R dpp_xor1(R x) {
   }
 }
 
+// Row stride of a wave tile, in values: L1 + 1 when L1 = R1, L1 + 2 when
+// L1 = 2 R1.  Pass 2 reads column pairs (2m + h) of rows k1 across the lane
+// pairs (k1, h): with an odd stride the rows of k1 and k1 + 1 fall on the
+// banks that h = 1 reads, with L1 + 2 they do not.
+__host__ __device__ constexpr uint32_t wave_fft_tile_stride(uint32_t logB) {
+  return (1u << (logB - logB / 2)) + 1u + (logB & 1u);
+}
+
 // LDS a wave needs for rounds of 2^logB points: its tile (64 / L1 rounds of
-// R1 rows of L1 + 1 values).
+// R1 rows).
 __host__ __device__ constexpr uint32_t wave_fft_tile_elems(uint32_t logB) {
-  return (64u >> (logB - logB / 2)) * (1u << (logB / 2)) * ((1u << (logB - logB / 2)) + 1u);
+  return (64u >> (logB - logB / 2)) * (1u << (logB / 2)) * wave_fft_tile_stride(logB);
 }
 
 // One chunk of up to 64 / L1 rounds of B = 2^(2C + E) points (E = 0 or 1)
@@ -158,10 +167,11 @@ __host__ __device__ constexpr uint32_t wave_fft_tile_elems(uint32_t logB) {
 template <typename R, int C, int E, class Row, class Inv>
 __device__ __forceinline__ void wave_fft_chunk(uint32_t nr, Row row, Inv inv, cplx<R>* tile, const cplx<R>* tw) {
   constexpr uint32_t R1 = 1u << C, L1 = R1 << E, B = R1 * L1, LPK = 1u << E;
+  constexpr uint32_t S = wave_fft_tile_stride(2 * C + E);
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t r = lane / L1, q = lane % L1;  // round slot, index within the round
   const bool live = r < nr;
-  cplx<R>* T = tile + r * R1 * (L1 + 1);
+  cplx<R>* T = tile + r * R1 * S;
   cplx<R> v[R1];
   // pass 1: lane n2 = q takes x[L1 n1 + n2]
   if (live) {
@@ -174,7 +184,7 @@ __device__ __forceinline__ void wave_fft_chunk(uint32_t nr, Row row, Inv inv, cp
   for (uint32_t k1 = 1; k1 < R1; ++k1) v[k1] = cmul(v[k1], tw_at(tw, q * k1, B));
   if (live) {
 #pragma unroll
-    for (uint32_t k1 = 0; k1 < R1; ++k1) T[k1 * (L1 + 1) + q] = v[k1];
+    for (uint32_t k1 = 0; k1 < R1; ++k1) T[k1 * S + q] = v[k1];
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -183,7 +193,7 @@ __device__ __forceinline__ void wave_fft_chunk(uint32_t nr, Row row, Inv inv, cp
   const uint32_t k1 = q / LPK, h = q % LPK;
   if (live) {
 #pragma unroll
-    for (uint32_t m = 0; m < R1; ++m) v[m] = T[k1 * (L1 + 1) + LPK * m + h];
+    for (uint32_t m = 0; m < R1; ++m) v[m] = T[k1 * S + LPK * m + h];
   }
   lane_dft<R, C>(v);  // R1-point DFT over m
   if constexpr (E == 1) {
