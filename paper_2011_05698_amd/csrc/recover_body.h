@@ -612,31 +612,37 @@ __device__ R loop_median(const cplx<R>* vs, uint32_t n) {
   return (n & 1u) ? lo : (lo + hi) * R(0.5);
 }
 
-// Per-(candidate, round) pass: theta_j as a binary angle and the
-// round-to-round magnitude test of the detection rule.
+// Per candidate: the round-to-round magnitude test of the detection rule
+// over rounds 1..R, then, for a candidate that passes it, theta_j of every
+// round as a binary angle (the location of a failed candidate is never
+// taken, so its angles are not formed).  One thread per candidate, its
+// rounds' values read in batches of kBatch.
 template <typename A, typename R>
 __device__ void angles_and_consistency(const cplx<R>* y0, const uint16_t* cand, const cplx<R>* rows, uint32_t ncand,
                                        uint32_t R_, bool fp64, R rho, A* th, uint8_t* bad) {
-  const uint32_t nitems = R_ * ncand;
-  for (uint32_t q0 = 0; q0 < nitems; q0 += kBatch * kRecThreads) {
-    cplx<R> a[kBatch], b[kBatch];
+  for (uint32_t c = threadIdx.x; c < ncand; c += kRecThreads) {
+    const cplx<R> a = y0[cand[c]];
+    const R m0 = sqrt(a.re * a.re + a.im * a.im);
+    bool fail = false;
+    for (uint32_t j0 = 0; j0 < R_; j0 += kBatch) {
+      cplx<R> b[kBatch];
 #pragma unroll
-    for (int e = 0; e < kBatch; ++e) {
-      const uint32_t q = q0 + uint32_t(e) * kRecThreads + threadIdx.x;
-      if (q < nitems) {
-        const uint32_t c = q % ncand;
-        a[e] = y0[cand[c]];
-        b[e] = rows[q];
-      }
+      for (int e = 0; e < kBatch; ++e)
+        if (j0 + uint32_t(e) < R_) b[e] = rows[(j0 + uint32_t(e)) * ncand + c];
+#pragma unroll
+      for (int e = 0; e < kBatch; ++e)
+        if (j0 + uint32_t(e) < R_ && fabs(sqrt(b[e].re * b[e].re + b[e].im * b[e].im) - m0) > rho * m0) fail = true;
     }
+    bad[c] = fail ? 1 : 0;
+    if (fail) continue;
+    for (uint32_t j0 = 0; j0 < R_; j0 += kBatch) {
+      cplx<R> b[kBatch];
 #pragma unroll
-    for (int e = 0; e < kBatch; ++e) {
-      const uint32_t q = q0 + uint32_t(e) * kRecThreads + threadIdx.x;
-      if (q < nitems) {
-        th[q] = theta_bin<A>(a[e], b[e], fp64);
-        const R m0 = sqrt(a[e].re * a[e].re + a[e].im * a[e].im);
-        if (fabs(sqrt(b[e].re * b[e].re + b[e].im * b[e].im) - m0) > rho * m0) bad[q % ncand] = 1;
-      }
+      for (int e = 0; e < kBatch; ++e)
+        if (j0 + uint32_t(e) < R_) b[e] = rows[(j0 + uint32_t(e)) * ncand + c];
+#pragma unroll
+      for (int e = 0; e < kBatch; ++e)
+        if (j0 + uint32_t(e) < R_) th[(j0 + uint32_t(e)) * ncand + c] = theta_bin<A>(a, b[e], fp64);
     }
   }
 }
@@ -750,11 +756,11 @@ __device__ void recover_signal(const SignalDesc& sd, RecoverShared<R>& sh) {
     }
     cplx<R>* y0 = ar.take<cplx<R>>(B);
     uint32_t* cu = ar.take<uint32_t>(B);  // located position per bucket, or kNone
-    R* gq = nullptr;                      // window weight per (sorted entry, reachable bucket)
+    R* gw = nullptr;                      // window weight per (entry, reachable bucket), by entry index
     RunBounds* run = nullptr;
     cplx<R>* w0 = nullptr;                // v exp(-2 pi i T_0 u / N) per sorted entry
     if (subtract) {
-      gq = ar.take<R>(uint64_t(nst) * nslot);
+      gw = ar.take<R>(uint64_t(nst) * nslot);
       run = ar.take<RunBounds>(B);
       w0 = ar.take<cplx<R>>(nst);
     }
@@ -764,7 +770,6 @@ __device__ void recover_signal(const SignalDesc& sd, RecoverShared<R>& sh) {
     uint32_t* raw_u = nst > 0 ? ar.take<uint32_t>(nst) : nullptr;
     cplx<R>* raw_v = nst > 0 ? ar.take<cplx<R>>(nst) : nullptr;
     uint64_t* tmp = nst > 0 ? ar.take<uint64_t>(nst) : nullptr;
-    R* graw = subtract ? ar.take<R>(uint64_t(nst) * nslot) : nullptr;  // weights by entry
     for (uint32_t c = tid; c < npow && nst > 0; c += NT) cend[c] = 0;
     {
       const uint32_t nload = max(B, nst);
@@ -819,7 +824,7 @@ __device__ void recover_signal(const SignalDesc& sd, RecoverShared<R>& sh) {
 #pragma unroll
           for (int e = 0; e < kBatch; ++e) {
             const uint32_t q = q0 + uint32_t(e) * NT + tid;
-            if (q < ngq) graw[q] = g[e];
+            if (q < ngq) gw[q] = g[e];
           }
         }
       }
@@ -841,7 +846,6 @@ __device__ void recover_signal(const SignalDesc& sd, RecoverShared<R>& sh) {
         const cplx<R> v = raw_v[k];
         sv[q] = v;
         if (subtract) {
-          for (uint32_t s2 = 0; s2 < nslot; ++s2) gq[q * nslot + s2] = graw[k * nslot + s2];
           // round 0's value x phase, once per entry
           w0[q] = cmul(v, expi<R>((it->T[0] * uint32_t(key >> 32)) & nmask, logN, R(-1)));
         }
@@ -886,9 +890,10 @@ __device__ void recover_signal(const SignalDesc& sd, RecoverShared<R>& sh) {
       for (uint32_t v = lane; v < rb.count; v += S_) {
         uint32_t q = rb.first + v;
         q = q >= nst ? q - nst : q;
-        const uint32_t u = uint32_t(sk[q] >> 32);
+        const uint64_t key = sk[q];
+        const uint32_t u = uint32_t(key >> 32);
         const uint32_t slot = (i - uint32_t(first_bucket(u, D, it->logL))) & (B - 1);
-        const R g = gq[q * nslot + slot];
+        const R g = gw[uint32_t(key) * nslot + slot];
         const cplx<R> w = wq ? wq[q] : cmul(sv[q], expi<R>((Tj * u) & nmask, logN, R(-1)));
         acc = cadd(acc, cscale(w, g));
       }
@@ -973,26 +978,22 @@ __device__ void recover_signal(const SignalDesc& sd, RecoverShared<R>& sh) {
     }
     uint8_t* bad = ar.take<uint8_t>(ncand);  // failed the round-to-round test
     cplx<R>* rows = ar.take<cplx<R>>(uint64_t(R_) * ncand);  // round j of candidate c at (j-1) ncand + c
-    for (uint32_t c = tid; c < ncand; c += NT) bad[c] = 0;
     __syncthreads();
 
     // ---- 5. rounds 1..R of the candidates, minus the store's contributions ----
     const uint32_t nitems = R_ * ncand;
     if (!subtract) {
-      for (uint32_t q0 = 0; q0 < nitems; q0 += kBatchY * NT) {
-        cplx<R> v[kBatchY];
+      // one thread per candidate: its rounds' bucket values, kBatchY loads in flight
+      for (uint32_t c = tid; c < ncand; c += NT) {
+        const uint32_t i = cand[c];
+        for (uint32_t j0 = 0; j0 < R_; j0 += kBatchY) {
+          cplx<R> v[kBatchY];
 #pragma unroll
-        for (int e = 0; e < kBatchY; ++e) {
-          const uint32_t q = q0 + uint32_t(e) * NT + tid;
-          if (q < nitems) {
-            const uint32_t j = 1 + q / ncand, c = q - (j - 1) * ncand;
-            v[e] = Yg[size_t(j) * B + cand[c]];
-          }
-        }
+          for (int e = 0; e < kBatchY; ++e)
+            if (j0 + uint32_t(e) < R_) v[e] = Yg[size_t(j0 + uint32_t(e) + 1) * B + i];
 #pragma unroll
-        for (int e = 0; e < kBatchY; ++e) {
-          const uint32_t q = q0 + uint32_t(e) * NT + tid;
-          if (q < nitems) rows[q] = v[e];
+          for (int e = 0; e < kBatchY; ++e)
+            if (j0 + uint32_t(e) < R_) rows[(j0 + uint32_t(e)) * ncand + c] = v[e];
         }
       }
     } else {
@@ -1002,16 +1003,16 @@ __device__ void recover_signal(const SignalDesc& sd, RecoverShared<R>& sh) {
       const uint32_t team = tid / S2, lane = tid & (S2 - 1), nteams = NT / S2;
       for (uint32_t base_q = 0; base_q < nitems; base_q += nteams) {  // uniform trip count per wave
         const uint32_t q = base_q + team;
-        cplx<R> acc{0, 0};
-        uint32_t j = 1, i = 0;
+        cplx<R> acc{0, 0}, yv{0, 0};
         if (q < nitems) {
-          j = 1 + q / ncand;
-          i = cand[q - (j - 1) * ncand];
+          const uint32_t j = 1 + q / ncand;
+          const uint32_t i = cand[q - (j - 1) * ncand];
+          if (lane == S2 - 1) yv = Yg[size_t(j) * B + i];  // in flight during the run sum
           acc = run_sum(i, it->T[j], nullptr, lane, S2);
         }
         acc.re = team_sum(acc.re, S2);
         acc.im = team_sum(acc.im, S2);
-        if (q < nitems && lane == S2 - 1) rows[q] = csub(Yg[size_t(j) * B + i], acc);
+        if (q < nitems && lane == S2 - 1) rows[q] = csub(yv, acc);
       }
     }
     __syncthreads();
