@@ -1,0 +1,146 @@
+"""The recovery kernel's body on the CPU (tests/emu): no GPU is touched.
+
+tests/emu/hip_emu.h emulates the HIP device code the recovery uses (one host
+thread per work item, barriers, DPP moves per wavefront of 64 threads);
+tests/emu/recover_emu.cpp runs recover_body.h, the code the GPU kernels
+run, on one signal whose bucket values come from the oracle's HashToBins
+(built twice: plain host arithmetic, and with fused multiply-adds wherever
+the compiler can contract, as the GPU compiler does),
+with every buffer it reads or writes (bucket values, workspace, plan
+tables, outputs, the workgroup's LDS) placed against an inaccessible guard
+page, past its end in one run and before its start in another.  Any access
+outside a buffer stops the program and names the buffer; a barrier or wave
+move that not every thread reaches is reported as well.  The result must be
+the oracle's support, with values within the GPU tests' tolerance.
+
+The first case is the end-to-end case whose first GPU run, with an earlier
+recovery kernel since replaced, faulted the GPU (complex128, (l, q) =
+(16, 1)); the others are its siblings, a larger shape, and the direct
+location and vote options.
+"""
+
+import hashlib
+import os
+import shutil
+import subprocess
+import struct
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle.sfft_oracle as O
+from paper_2011_05698_amd.signals import SignalSpec, make_signal
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2011_05698_amd", "csrc")
+EMU = os.path.join(ROOT, "tests", "emu")
+BUILD = os.path.join(ROOT, "_build", "emu")
+
+DTYPES = {"c64": 0, "c128": 1}
+
+
+FLAVOURS = {
+    # plain host arithmetic, and fused multiply-adds wherever the compiler can
+    # contract (as the GPU compiler does): decisions must not hinge on either
+    "plain": ["-O2"],
+    "fma": ["-O2", "-mfma", "-ffp-contract=fast"],
+}
+
+
+def _build(main, flavour):
+    """Builds an emulation program once per source state (host g++, no HIP)."""
+    srcs = [os.path.join(EMU, f) for f in ("recover_emu.cpp", "emu_selftest.cpp", "hip_emu.h", "guarded.h")]
+    srcs += [os.path.join(EMU, "include", "hip", "hip_runtime.h"), os.path.join(CSRC, "plan.cpp"),
+             os.path.join(ROOT, "include", "sfft.h")]
+    srcs += [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC)) if f.endswith(".h")]
+    h = hashlib.sha256(" ".join(FLAVOURS[flavour]).encode())
+    for f in srcs:
+        h.update(open(f, "rb").read())
+    exe = os.path.join(BUILD, f"{main}_{flavour}_{h.hexdigest()[:16]}")
+    if os.path.exists(exe):
+        return exe
+    gxx = shutil.which("g++")
+    if not gxx:
+        pytest.skip("g++ not found")
+    os.makedirs(BUILD, exist_ok=True)
+    tmp = exe + ".tmp"
+    extra = [os.path.join(CSRC, "plan.cpp")] if main == "recover_emu" else []
+    subprocess.run([gxx, "-std=c++17", *FLAVOURS[flavour], "-g", "-pthread", "-Wno-unknown-pragmas",
+                    "-I", os.path.join(EMU, "include"), "-I", EMU, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+                    os.path.join(EMU, main + ".cpp"), *extra, "-o", tmp], check=True, capture_output=True)
+    os.replace(tmp, exe)
+    return exe
+
+
+def test_emulation_reports_faults_and_divergence():
+    """The emulation itself: a write one element past or before a guarded
+    buffer stops the program and names the buffer; a wave move that one
+    lane skips is reported; the kernel's DPP team sums, wave extrema and
+    wave scan equal their definitions."""
+    exe = _build("emu_selftest", "plain")
+    for what, byte in (("fault-after", "400"), ("fault-before", "-4")):
+        r = subprocess.run([exe, what], capture_output=True, text=True, timeout=60)
+        assert r.returncode == 86, (what, r.returncode, r.stdout, r.stderr)
+        assert f"access at byte {byte} of self-test buffer" in r.stderr
+    env = dict(os.environ, EMU_BARRIER_TIMEOUT_S="2")
+    r = subprocess.run([exe, "diverge"], capture_output=True, text=True, timeout=60, env=env)
+    assert r.returncode == 87 and "barrier not reached by every thread" in r.stderr, (r.returncode, r.stderr)
+    r = subprocess.run([exe, "dpp"], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0 and "dpp: 0 mismatches" in r.stdout, (r.stdout, r.stderr)
+
+
+def oracle_buckets(x, P):
+    """Bucket values of every round of every iteration, in the plan's layout."""
+    return np.concatenate([np.concatenate([O.hash_to_bins(x, it.sigma, it.T[j], it.G, it.B) for j in range(it.R + 1)])
+                           for it in P.iters])
+
+
+def run_emulated(tmp_path, y, N, K, B, w, M, l, q, delta, seed, dtype, guard_mode, flavour, location=0, combine=0):
+    exe = _build("recover_emu", flavour)
+    inp, out = tmp_path / f"in{guard_mode}.bin", tmp_path / f"out{guard_mode}_{flavour}.bin"
+    y = np.asarray(y, dtype=np.complex128)
+    with open(inp, "wb") as f:
+        f.write(struct.pack("<qqqqiiddQiiiiq", N, K, B, w, M, l, float(q), delta, seed, DTYPES[dtype], location,
+                            combine, guard_mode, len(y)))
+        f.write(np.stack([y.real, y.imag], axis=1).astype("<f8").tobytes())
+    r = subprocess.run([exe, str(inp), str(out)], capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, f"exit {r.returncode}: {r.stdout[-2000:]} {r.stderr[-2000:]}"
+    data = open(out, "rb").read()
+    c = struct.unpack_from("<q", data)[0]
+    rec = np.frombuffer(data[8:], dtype=np.dtype([("f", "<i8"), ("re", "<f8"), ("im", "<f8")]), count=c)
+    return rec["f"].copy(), rec["re"] + 1j * rec["im"]
+
+
+CASES = [
+    # N, K, B, w, loops, l, q, delta, dtype, signal seed, plan seed, location, combine
+    (2 ** 14, 50, 512, 7169, 8, 16, Fraction(1), 1e-8, "c128", 101, 102, "multiscale", "sum"),
+    (2 ** 14, 50, 512, 7169, 8, 4, Fraction(1, 4), 1e-8, "c128", 101, 102, "multiscale", "sum"),
+    (2 ** 14, 50, 512, 7169, 8, 16, Fraction(1), 1e-8, "c64", 101, 102, "multiscale", "sum"),
+    (2 ** 16, 200, 512, 8193, 10, 16, Fraction(1), 1e-6, "c64", 9, 10, "multiscale", "sum"),
+    (2 ** 16, 200, 512, 8193, 10, 16, Fraction(1), 1e-6, "c128", 9, 10, "multiscale", "sum"),
+    (2 ** 14, 50, 512, 7169, 8, 16, Fraction(1), 1e-6, "c64", 131, 132, "direct", "sum"),
+    (2 ** 14, 50, 512, 7169, 8, 16, Fraction(1), 1e-6, "c128", 141, 142, "multiscale", "vote"),
+]
+
+
+@pytest.mark.parametrize("flavour", sorted(FLAVOURS))
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"N{c[0]}_K{c[1]}_l{c[5]}_q{c[6]}_{c[8]}_{c[11]}_{c[12]}")
+def test_emulated_recovery_in_bounds_and_exact(tmp_path, case, flavour):
+    N, K, B, w, M, l, q, delta, dt, ss, ps, loc, comb = case
+    x, sup, _ = make_signal(SignalSpec(N, K, ss))
+    P = O.make_plan(N, K, B, w, M, l, q, delta, seed=ps, location=loc, combine=comb)
+    y = oracle_buckets(x, P)
+    if dt == "c64":
+        y = y.astype(np.complex64)
+    oidx, oval, _ = O.sfft(x, P)
+    if loc == "multiscale" and comb == "sum":
+        assert np.array_equal(oidx, np.sort(sup))
+    tol = 1e-10 if dt == "c128" else 1e-4
+    codes = dict(location={"multiscale": 0, "direct": 1}[loc], combine={"sum": 0, "vote": 1}[comb])
+    for mode in (0, 1):  # guard pages after, then before, every buffer
+        gidx, gval = run_emulated(tmp_path, y, N, K, B, w, M, l, q, delta, ps, dt, mode, flavour, **codes)
+        assert np.array_equal(gidx, oidx), set(gidx) ^ set(oidx)
+        err = np.linalg.norm(gval - oval) / np.linalg.norm(oval)
+        assert err <= tol, err
+        assert np.max(np.abs(gval - oval) / np.abs(oval)) <= 10 * tol
