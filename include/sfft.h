@@ -329,8 +329,10 @@ sfft_status sfft_batch_set_fold_config(sfft_batch_t b, const sfft_fold_config* c
  *                      and FP16 storage, B <= 4096 for complex128.  A wait
  *                      that has not ended after a bounded number of polls
  *                      (seconds) gives up: that signal's count reads -2.
- * Every setting gives bit-identical results.  Setting a tuning waits for the
- * batch's last replay and drops its graph, like sfft_batch_set_fold_config.
+ * Every STAGES setting gives bit-identical results; FUSED runs the bucket
+ * DFT as the LDS radix-2^2 pass for every B, so its results agree with
+ * them to rounding.  Setting a tuning waits for the batch's last replay and
+ * drops its graph, like sfft_batch_set_fold_config.
  * SFFT_ERR_PARAM for a value outside the lists, or (FUSED) fused_chunk
  * outside 1 .. the number of signals (or groups); SFFT_ERR_UNSUPPORTED for
  * FUSED where it is not available.
