@@ -739,7 +739,9 @@ def main():
     if XT is not None and args.layout != "position-major":
         del XT
 
-    # ---- roofline of the dominant kernel (the fold) ----
+    # ---- roofline of the gather-fold, the kernel whose HBM rate the metric
+    # names; the longest stage is the recovery, bound by dependent latency
+    # rather than by HBM or arithmetic (stage_roofline below) ----
     bytes_per_sample = {"c64": 8, "f16x2": 4, "c128": 16}[dt]
     out_bytes = 16 if dt == "c128" else 8
     alg_bytes = n * (plan.samples * bytes_per_sample + plan.yhat_elems * out_bytes)
@@ -753,6 +755,8 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
                 "kernel": fold_kernel,
+                "why_this_kernel": "the gather-fold, whose HBM rate the metric names; the longest stage "
+                                   "(the recovery) is latency-bound, see stage_roofline",
                 "alg_bytes_per_launch": alg_bytes,
                 "avg_launch_ms": round(stage_ms[0], 5)}
     if traffic:
