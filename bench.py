@@ -73,6 +73,9 @@ def make_batch(torch, n, N, K, snr, dtype, dev, seed0):
     return X, scales
 
 
+FOLD_SOURCES = ("fold.hip", "fold_body.h", "device_common.h", "internal.h", "api.hip")
+
+
 def measured_traffic(workload_tag):
     """HBM bytes per fold launch from the committed rocprofv3 summary of this
     workload and layout, if the fold kernel and its launch order are the ones
@@ -88,9 +91,10 @@ def measured_traffic(workload_tag):
             continue
         k, v = line.split(None, 1)
         vals[k] = v.strip()
-    # the kernel (fold.hip) and the order its tiles are launched in (api.hip)
+    # the kernel (fold.hip, fold_body.h and the helpers and layout they use)
+    # and the order its tiles are launched in (api.hip)
     csrc = os.path.join(ROOT, "paper_2011_05698_amd", "csrc")
-    src = b"".join(open(os.path.join(csrc, f), "rb").read() for f in ("fold.hip", "api.hip"))
+    src = b"".join(open(os.path.join(csrc, f), "rb").read() for f in FOLD_SOURCES)
     if vals.get("fold_sources_sha256_16") != hashlib.sha256(src).hexdigest()[:16]:
         return None, "fold kernel or its launch order changed since the counters were taken"
     # the launch shape moves no bytes (every shape gathers the same samples), so

@@ -127,6 +127,11 @@ CASES_HASH = [
     (2 ** 16, 200, 512, 8193, 6, 16, Fraction(1), 1e-6, "c64"),
     (2 ** 12, 10, 64, 769, 4, 8, Fraction(3, 2), 1e-7, "c64"),
     (2 ** 16, 200, 512, 8193, 6, 16, Fraction(1), 1e-6, "f16x2"),
+    # every bucket-DFT size, halving from the first iteration's B down to 16:
+    # 2^14..2^4 in complex64 (the in-register wave path up to 2^11, the LDS
+    # pass above), 2^13..2^4 in complex128 (wave path up to 2^9)
+    (2 ** 17, 100, 16384, 65537, 11, 16, Fraction(1), 1e-6, "c64"),
+    (2 ** 16, 100, 8192, 32769, 10, 16, Fraction(1), 1e-6, "c128"),
 ]
 
 
