@@ -83,6 +83,7 @@ struct sfft_plan_s {
   unsigned char* d_ws = nullptr;
   uint32_t ntiles = 0, nitems = 0;
   FftGroups fft;
+  FoldSplit split;
   FoldConfig fold{8, 0};
 };
 
@@ -98,6 +99,7 @@ struct sfft_batch_s {
   std::vector<uint64_t> ws_off;
   uint32_t ntiles = 0, nitems = 0, max_B = 0;
   FftGroups fft;
+  FoldSplit split;                  // per-signal tiles: union tiles first (order_for_stages)
   std::vector<SignalDesc> bound;    // host copy of the uploaded descriptor table
   bool has_binding = false;
   hipGraph_t graph = nullptr;
@@ -173,31 +175,6 @@ void group_rounds(std::vector<RoundItem>& items, BOf b_of, int dtype, std::vecto
   fg.ngroups = uint32_t(groups.size());
 }
 
-// Work lists of one signal, signal-major: the fold covers the (R_m+1) x B_m
-// (round, bucket) items of every iteration in tiles of kFoldTile items.
-// When B_m >= kFoldTile the tiles go out in chunks of 8 bucket blocks: for
-// each round j, the blocks of round j that gather the same positions as the
-// chunk's round-0 blocks (bucket b + (T_j - T_0) mod B), so that tiles 8
-// dispatches apart (the same XCD) share the cache lines they gather.
-void build_work_lists(const HostPlan& hp, uint32_t sig, std::vector<FoldTile>& tiles, std::vector<RoundItem>& items) {
-  for (int m = 0; m < hp.loops; ++m) {
-    const IterDesc& d = hp.iters[m].d;
-    for (uint32_t j = 0; j <= d.R; ++j) items.push_back(RoundItem{sig, uint16_t(m), uint16_t(j)});
-    if (d.B < uint32_t(kFoldTile)) {
-      const uint32_t n = (d.R + 1) * d.B;
-      for (uint32_t i0 = 0; i0 < n; i0 += kFoldTile) tiles.push_back(FoldTile{sig, uint32_t(m), i0});
-      continue;
-    }
-    const uint32_t nb = d.B / kFoldTile;  // B and kFoldTile are powers of two
-    for (uint32_t c0 = 0; c0 < nb; c0 += 8)
-      for (uint32_t j = 0; j <= d.R; ++j) {
-        const uint32_t shift = ((d.T[j] - d.T[0]) & (d.B - 1)) / kFoldTile;  // B divides N and 2^32
-        for (uint32_t blk = c0; blk < c0 + 8 && blk < nb; ++blk)
-          tiles.push_back(FoldTile{sig, uint32_t(m), j * d.B + ((blk + shift) % nb) * kFoldTile});
-      }
-  }
-}
-
 bool valid_fold(const sfft_fold_config* c) {
   return c && (c->unroll == 8 || c->unroll == 16 || c->unroll == 24) && c->wg_per_cu >= 0 && c->wg_per_cu <= 8 &&
          c->wg_per_cu != 1;
@@ -217,6 +194,7 @@ sfft_status upload_plan(sfft_plan_t p) {
   std::vector<FoldTile> tiles;
   std::vector<RoundItem> items;
   build_work_lists(hp, 0, tiles, items);
+  p->split = order_for_stages(tiles);
   std::vector<FftGroup> groups;
   group_rounds(items, [&](const RoundItem& r) { return hp.iters[r.m].d.B; }, hp.dtype, groups, p->fft);
   p->ntiles = uint32_t(tiles.size());
@@ -326,7 +304,7 @@ uint32_t max_B(const HostPlan& hp) {
 }
 
 sfft_status run_hash(sfft_plan_t p, const SigArg& a, hipStream_t s) {
-  int e = launch_fold(p->hp.dtype, p->hp.kahan, p->fold, a, p->d_tiles, p->ntiles, s);
+  int e = launch_fold(p->hp.dtype, p->hp.kahan, p->fold, a, p->d_tiles, p->ntiles, p->split, s);
   if (e != hipSuccess) return hip_fail(hipError_t(e), "fold launch");
   e = launch_bucket_fft(p->hp.dtype, a, p->d_items, p->d_groups, p->fft, s);
   if (e != hipSuccess) return hip_fail(hipError_t(e), "bucket FFT launch");
@@ -393,7 +371,7 @@ int launch_batch_fold(const sfft_batch_s* b, const FoldConfig& cfg, hipStream_t 
   if (b->interleaved)
     return launch_fold_interleaved(b->dtype, b->kahan, cfg.unroll, b->d_sigs, uint32_t(b->plans.size()), b->d_tiles,
                                    b->ntiles, s);
-  return launch_fold(b->dtype, b->kahan, cfg, table_arg(b), b->d_tiles, b->ntiles, s);
+  return launch_fold(b->dtype, b->kahan, cfg, table_arg(b), b->d_tiles, b->ntiles, b->split, s);
 }
 
 }  // namespace
@@ -638,6 +616,8 @@ sfft_status create_batch_impl(sfft_batch_t* out, const sfft_plan_t* h_plans, int
     interleaved_tiles(h_plans[0]->hp, b->ngroups, tiles);
     b->group_tiles.resize(b->ngroups);
     for (const FoldTile& t : tiles) b->group_tiles[t.sig].push_back(t);
+  } else {
+    b->split = order_for_stages(tiles);  // group_tiles keep each signal's own order for the fused launch
   }
   b->nfgroups = uint32_t(b->group_tiles.size());
   b->h_items = items;

@@ -1,4 +1,5 @@
-// Stage kernels of the fold: one workgroup per tile (device bodies in fold_body.h).
+// Stage kernels of the fold: one workgroup per tile (device bodies in
+// fold_body.h); union tiles and one-round tiles in kernels of their own.
 #include "fold_body.h"
 
 namespace sfft {
@@ -7,6 +8,12 @@ template <class Ld, bool KAHAN, int U>
 __global__ __launch_bounds__(kFoldTile) void fold_kernel(SigArg arg, const FoldTile* __restrict__ tiles) {
   const FoldTile tl = tiles[blockIdx.x];
   fold_tile<Ld, KAHAN, U>(load_signal(arg, tl.sig), tl);
+}
+
+template <class Ld, bool KAHAN, int U, int NU>
+__global__ __launch_bounds__(kFoldTile) void fold_union_kernel(SigArg arg, const FoldTile* __restrict__ tiles) {
+  const FoldTile tl = tiles[blockIdx.x];
+  fold_union<Ld, KAHAN, U, NU>(load_signal(arg, tl.sig), fold_tile_iter(tl.m), tl.i0);
 }
 
 template <class Ld, bool KAHAN, int U>
@@ -23,29 +30,45 @@ int fold_lds_bytes(int wg_per_cu) {
   return per > 65536 ? 65536 : per;
 }
 
+template <class Ld, bool KAHAN, int U>
+static void launch_one(uint32_t nu, uint32_t n, size_t lds, hipStream_t s, const SigArg& sig, const FoldTile* t) {
+  const dim3 grid(n), block(kFoldTile);
+  if (nu == 2) hipLaunchKernelGGL((fold_union_kernel<Ld, KAHAN, U, 2>), grid, block, lds, s, sig, t);
+  else if (nu == 3) hipLaunchKernelGGL((fold_union_kernel<Ld, KAHAN, U, 3>), grid, block, lds, s, sig, t);
+  else if (nu == 4) hipLaunchKernelGGL((fold_union_kernel<Ld, KAHAN, U, 4>), grid, block, lds, s, sig, t);
+  else hipLaunchKernelGGL((fold_kernel<Ld, KAHAN, U>), grid, block, lds, s, sig, t);
+}
+
 template <class Ld, bool KAHAN>
-static void launch_u(int unroll, dim3 grid, dim3 block, size_t lds, hipStream_t s, const SigArg& sig,
-                     const FoldTile* d_tiles) {
-  if (unroll >= 24) hipLaunchKernelGGL((fold_kernel<Ld, KAHAN, 24>), grid, block, lds, s, sig, d_tiles);
-  else if (unroll >= 16) hipLaunchKernelGGL((fold_kernel<Ld, KAHAN, 16>), grid, block, lds, s, sig, d_tiles);
-  else hipLaunchKernelGGL((fold_kernel<Ld, KAHAN, 8>), grid, block, lds, s, sig, d_tiles);
+static void launch_u(int unroll, uint32_t nu, uint32_t n, size_t lds, hipStream_t s, const SigArg& sig,
+                     const FoldTile* t) {
+  if (unroll >= 24) launch_one<Ld, KAHAN, 24>(nu, n, lds, s, sig, t);
+  else if (unroll >= 16) launch_one<Ld, KAHAN, 16>(nu, n, lds, s, sig, t);
+  else launch_one<Ld, KAHAN, 8>(nu, n, lds, s, sig, t);
 }
 
 int launch_fold(int dtype, int kahan, const FoldConfig& cfg, const SigArg& sig, const FoldTile* d_tiles,
-                uint32_t ntiles, void* stream) {
-  if (ntiles == 0) return hipSuccess;
+                uint32_t ntiles, const FoldSplit& split, void* stream) {
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const dim3 grid(ntiles), block(kFoldTile);
   const size_t lds = size_t(fold_lds_bytes(cfg.wg_per_cu));
-  if (dtype == SFFT_C128) {
-    if (kahan) launch_u<LoadC128, true>(cfg.unroll, grid, block, lds, s, sig, d_tiles);
-    else launch_u<LoadC128, false>(cfg.unroll, grid, block, lds, s, sig, d_tiles);
-  } else if (dtype == SFFT_F16X2_SCALED) {
-    if (kahan) launch_u<LoadF16, true>(cfg.unroll, grid, block, lds, s, sig, d_tiles);
-    else launch_u<LoadF16, false>(cfg.unroll, grid, block, lds, s, sig, d_tiles);
-  } else {
-    if (kahan) launch_u<LoadC64, true>(cfg.unroll, grid, block, lds, s, sig, d_tiles);
-    else launch_u<LoadC64, false>(cfg.unroll, grid, block, lds, s, sig, d_tiles);
+  uint32_t at = 0;
+  for (uint32_t k = 0; k <= kMaxUnionRounds - 1; ++k) {
+    // union tiles of k + 2 rounds, then (k = kMaxUnionRounds - 1) the one-round tiles
+    const uint32_t nu = k < kMaxUnionRounds - 1 ? k + 2 : 1;
+    const uint32_t n = k < kMaxUnionRounds - 1 ? split.nunion[k] : ntiles - at;
+    if (n == 0) continue;
+    const FoldTile* t = d_tiles + at;
+    at += n;
+    if (dtype == SFFT_C128) {
+      if (kahan) launch_u<LoadC128, true>(cfg.unroll, nu, n, lds, s, sig, t);
+      else launch_u<LoadC128, false>(cfg.unroll, nu, n, lds, s, sig, t);
+    } else if (dtype == SFFT_F16X2_SCALED) {
+      if (kahan) launch_u<LoadF16, true>(cfg.unroll, nu, n, lds, s, sig, t);
+      else launch_u<LoadF16, false>(cfg.unroll, nu, n, lds, s, sig, t);
+    } else {
+      if (kahan) launch_u<LoadC64, true>(cfg.unroll, nu, n, lds, s, sig, t);
+      else launch_u<LoadC64, false>(cfg.unroll, nu, n, lds, s, sig, t);
+    }
   }
   return hipGetLastError();
 }

@@ -6,6 +6,16 @@
 // Index arithmetic is uint32 with wrap-around, exact because N divides 2^32.
 // Taps are fetched U at a time (predicated at the end) so that U independent
 // gathers are in flight per thread.
+//
+// Rounds of one iteration share sigma, so tap t of round j reads the sample
+// of tap t - d_j of round 0, d_j = T_j - T_0 mod N: when the offsets of
+// rounds 0..nu-1 step by less than w, their windows tile one interval of
+// round-0 taps, [-h - d_{nu-1}, h].  A union tile (fold_union) walks that
+// interval once per round-0 bucket b and adds each sample into every round
+// whose window holds it (round j's bucket is b + d_j mod B), so a sample
+// is gathered once for all of those rounds instead of once per round.  Each
+// round still takes its taps in increasing t with the same arithmetic, so
+// its sum is bit for bit the one-round tile's.
 #pragma once
 
 #include "device_common.h"
@@ -56,12 +66,76 @@ struct Acc {
   }
 };
 
-// One fold tile of one signal: thread threadIdx.x takes item tl.i0 + threadIdx.x.
+// Union tile of rounds 0..NU-1 of iteration m: thread threadIdx.x takes the
+// round-0 bucket b = i0 + threadIdx.x and writes bucket b + d_j mod B of
+// each round j < NU.
+template <class Ld, bool KAHAN, int U, int NU>
+__device__ __forceinline__ void fold_union(const SignalDesc& sd, uint32_t m, uint32_t i0) {
+  using R = typename Ld::R;
+  const PlanDesc* pd = sd.plan;
+  const IterDesc* it = pd->iters + m;
+  const uint32_t B = it->B;
+  const uint32_t b = i0 + threadIdx.x;
+  if (b >= B) return;
+  const uint32_t nmask = pd->N - 1;
+  const int32_t h = int32_t(it->h);
+  const uint32_t T0 = it->T[0];
+  const uint32_t sigma = it->sigma;
+  const R* __restrict__ G = reinterpret_cast<const R*>(pd->window) + it->win_off;
+  int32_t d[NU];  // d_j = T_j - T_0 mod N, ascending, d_{NU-1} + w <= N (host-checked)
+#pragma unroll
+  for (int j = 0; j < NU; ++j) d[j] = int32_t((it->T[j] - T0) & nmask);
+  // first round-0 tap t0 = b (mod B) with t0 >= lo; the interval is longer than B
+  const int32_t lo = -h - d[NU - 1];
+  const int32_t tf = lo + int32_t((b - uint32_t(lo)) & (B - 1));
+  const uint32_t ntaps = uint32_t(h - tf) / B + 1;
+  uint32_t idx = (sigma * (uint32_t(tf) - T0)) & nmask;
+  const uint32_t step = (sigma * B) & nmask;
+  Acc<R, KAHAN> acc[NU];
+  int32_t t0 = tf;
+  for (uint32_t k0 = 0; k0 < ntaps; k0 += U) {
+    cplx<R> s[U];
+    R g[U][NU];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      s[q] = k0 + q < ntaps ? Ld::load(sd.x, idx) : cplx<R>{0, 0};
+#pragma unroll
+      for (int j = 0; j < NU; ++j) {
+        const int32_t t = t0 + d[j];
+        g[q][j] = (k0 + q < ntaps && t >= -h && t <= h) ? G[t < 0 ? -t : t] : R(0);
+      }
+      idx = (idx + step) & nmask;
+      t0 += int32_t(B);
+    }
+    // round j's taps in increasing t; taps outside its window are not added
+    // (a one-round tile adds exact zeros there, which leave a sum unchanged)
+    int32_t tq = t0 - int32_t(U) * int32_t(B);
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+#pragma unroll
+      for (int j = 0; j < NU; ++j) {
+        const int32_t t = tq + d[j];
+        if (k0 + q < ntaps && t >= -h && t <= h) acc[j].add(g[q][j], s[q]);
+      }
+      tq += int32_t(B);
+    }
+  }
+  cplx<R>* Y = reinterpret_cast<cplx<R>*>(sd.y) + it->y_off;
+#pragma unroll
+  for (int j = 0; j < NU; ++j) {
+    cplx<R> out{acc[j].re, acc[j].im};
+    if (Ld::kScaled) out = cscale(out, R(sd.scale));
+    Y[(uint32_t(j) << it->logB) + ((b + uint32_t(d[j])) & (B - 1))] = out;
+  }
+}
+
+// One fold tile of one signal (not a union tile): thread threadIdx.x takes
+// item tl.i0 + threadIdx.x.
 template <class Ld, bool KAHAN, int U>
 __device__ __forceinline__ void fold_tile(const SignalDesc& sd, const FoldTile& tl) {
   using R = typename Ld::R;
   const PlanDesc* pd = sd.plan;
-  const IterDesc* it = pd->iters + tl.m;
+  const IterDesc* it = pd->iters + fold_tile_iter(tl.m);
   const uint32_t B = it->B, logB = it->logB;
   const uint32_t item = tl.i0 + threadIdx.x;
   if (item >= ((it->R + 1) << logB)) return;
@@ -101,6 +175,16 @@ __device__ __forceinline__ void fold_tile(const SignalDesc& sd, const FoldTile& 
   if (Ld::kScaled) out = cscale(out, R(sd.scale));
   cplx<R>* Y = reinterpret_cast<cplx<R>*>(sd.y) + it->y_off;
   Y[item] = out;  // item = j * B + b: row j of the iteration's (R+1) x B block
+}
+
+// Any per-signal fold tile: a union tile of its round count, or a one-round tile.
+template <class Ld, bool KAHAN, int U>
+__device__ __forceinline__ void fold_tile_any(const SignalDesc& sd, const FoldTile& tl) {
+  const uint32_t nu = fold_tile_rounds(tl.m), m = fold_tile_iter(tl.m);
+  if (nu == 2) fold_union<Ld, KAHAN, U, 2>(sd, m, tl.i0);
+  else if (nu == 3) fold_union<Ld, KAHAN, U, 3>(sd, m, tl.i0);
+  else if (nu >= 4) fold_union<Ld, KAHAN, U, 4>(sd, m, tl.i0);
+  else fold_tile<Ld, KAHAN, U>(sd, tl);
 }
 
 // Position-major batch: the signals share one plan and sample c of signal s

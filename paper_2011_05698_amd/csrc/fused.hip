@@ -73,7 +73,7 @@ __global__ __launch_bounds__(kRecThreads, 2) void fused_kernel(FusedArgs a) {
     if (f.kind == kFusedFold) {
       const FoldTile tl{f.grp, f.m, f.i0};
       if (PM) fold_tile_ilv<Ld, KAHAN, kFusedUnroll>(a.table, a.nsig, tl, *reinterpret_cast<IlvShared<R>*>(sh.buf));
-      else fold_tile<Ld, KAHAN, kFusedUnroll>(a.table[f.grp], tl);
+      else fold_tile_any<Ld, KAHAN, kFusedUnroll>(a.table[f.grp], tl);
       __threadfence();  // this thread's bucket values, visible device-wide
       __syncthreads();
       if (tid == 0) atomicAdd(done + f.grp, 1u);

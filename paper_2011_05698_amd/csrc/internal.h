@@ -85,9 +85,16 @@ struct SigArg {
 // Work items of the stage kernels.
 struct FoldTile {                  // fold items [i0, i0 + kFoldTile) of iteration m; item = j * B_m + b
   uint32_t sig;
-  uint32_t m;
+  uint32_t m;                      // iteration in the low 16 bits; a union tile's round count above
   uint32_t i0;
 };
+// A union tile gathers rounds 0..nu-1 of an iteration together (nu >= 2):
+// its items are the round-0 buckets [i0, i0 + kFoldTile), and each thread
+// writes its bucket's value in every one of those rounds (fold_body.h).
+constexpr uint32_t kMaxUnionRounds = 4;
+constexpr uint32_t fold_tile_iter(uint32_t m) { return m & 0xFFFFu; }
+constexpr uint32_t fold_tile_rounds(uint32_t m) { return m >> 16; }
+constexpr uint32_t fold_tile_code(uint32_t m, uint32_t nu) { return m | (nu << 16); }
 struct RoundItem {                 // one (signal, iteration, round)
   uint32_t sig;
   uint16_t m, j;
@@ -137,6 +144,21 @@ sfft_status build_host_plan(HostPlan& hp, int64_t N, int64_t K, int64_t B, int64
 // Workspace layout of one signal (fills the off_* fields of desc).
 void layout_workspace(HostPlan& hp);
 
+// Rounds 0..nu-1 of iteration d that a per-signal fold gathers in one union
+// tile: the leading rounds whose offsets d_j = T_j - T_0 mod N ascend in
+// steps shorter than w (so their windows cover one interval of round-0 taps
+// without a gap), at most kMaxUnionRounds, with d_{nu-1} + w <= N; 1 when
+// B is below a fold tile or no round overlaps round 0.
+uint32_t union_rounds(const IterDesc& d, uint32_t N);
+
+struct FoldSplit;
+// Appends the work lists of signal `sig` of a per-signal launch: its fold
+// tiles (union tiles included) and its (iteration, round) bucket-DFT items.
+void build_work_lists(const HostPlan& hp, uint32_t sig, std::vector<FoldTile>& tiles, std::vector<RoundItem>& items);
+// Orders per-signal fold tiles for the stage launches (FoldSplit) and counts
+// the union tiles of each round count.
+FoldSplit order_for_stages(std::vector<FoldTile>& tiles);
+
 // Bytes of the recovery's work area (arrays of one iteration that do not fit
 // in LDS, or the final top-K keys), for any iteration of the plan: every
 // array at its largest size, each rounded up to 16 bytes.  cb and rb are the
@@ -179,8 +201,14 @@ struct FoldConfig {
 int fold_lds_bytes(int wg_per_cu);
 constexpr int kIlvItems = 16;      // (round, bucket) items per position-major fold workgroup
 constexpr int kIlvSigs = 64;       // signals per position-major fold workgroup, one per lane
+// The per-signal stage launches take the union tiles first, by round count
+// (nunion[k] tiles uniting k + 2 rounds, each count in its own launch), then
+// the one-round tiles: each kernel keeps the registers of its own loop.
+struct FoldSplit {
+  uint32_t nunion[kMaxUnionRounds - 1] = {};
+};
 int launch_fold(int dtype, int kahan, const FoldConfig& cfg, const SigArg& sig, const FoldTile* d_tiles,
-                uint32_t ntiles, void* stream);
+                uint32_t ntiles, const FoldSplit& split, void* stream);
 // Position-major batch (one plan; sample c of signal s at table[s].x + c * ld,
 // with table[s].x = table[0].x + s): tiles of kIlvItems items x kIlvSigs
 // signals, FoldTile.sig = index of the signal group.

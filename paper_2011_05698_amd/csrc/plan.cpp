@@ -294,4 +294,64 @@ void layout_workspace(HostPlan& hp) {
   pd.ws_bytes = off;
 }
 
+uint32_t union_rounds(const IterDesc& d, uint32_t N) {
+  if (d.B < uint32_t(kFoldTile)) return 1;
+  const uint64_t w = d.w;
+  uint32_t nu = 1;
+  uint64_t prev = 0;
+  for (uint32_t j = 1; j <= d.R && nu < kMaxUnionRounds; ++j) {
+    const uint64_t dj = (d.T[j] - d.T[0]) & (N - 1);
+    if (dj < prev || dj - prev >= w || dj + w > N) break;
+    prev = dj;
+    ++nu;
+  }
+  return nu;
+}
+
+// Work lists of one signal, signal-major: the fold covers the (R_m+1) x B_m
+// (round, bucket) items of every iteration in tiles of kFoldTile items.
+// When B_m >= kFoldTile, the rounds whose windows overlap round 0's go into
+// union tiles (union_rounds), which gather each sample once for all of them,
+// and the tiles go out in chunks of 8 bucket blocks: for each round j, the
+// blocks of round j that gather the same positions as the chunk's round-0
+// blocks (bucket b + (T_j - T_0) mod B), so that tiles 8 dispatches apart
+// (the same XCD) share the cache lines they gather.
+void build_work_lists(const HostPlan& hp, uint32_t sig, std::vector<FoldTile>& tiles, std::vector<RoundItem>& items) {
+  for (int m = 0; m < hp.loops; ++m) {
+    const IterDesc& d = hp.iters[m].d;
+    for (uint32_t j = 0; j <= d.R; ++j) items.push_back(RoundItem{sig, uint16_t(m), uint16_t(j)});
+    if (d.B < uint32_t(kFoldTile)) {
+      const uint32_t n = (d.R + 1) * d.B;
+      for (uint32_t i0 = 0; i0 < n; i0 += kFoldTile) tiles.push_back(FoldTile{sig, uint32_t(m), i0});
+      continue;
+    }
+    const uint32_t nu = union_rounds(d, uint32_t(hp.N));
+    const uint32_t nb = d.B / kFoldTile;  // B and kFoldTile are powers of two
+    for (uint32_t c0 = 0; c0 < nb; c0 += 8) {
+      if (nu > 1)
+        for (uint32_t blk = c0; blk < c0 + 8 && blk < nb; ++blk)
+          tiles.push_back(FoldTile{sig, fold_tile_code(uint32_t(m), nu), blk * kFoldTile});
+      for (uint32_t j = nu > 1 ? nu : 0; j <= d.R; ++j) {
+        const uint32_t shift = ((d.T[j] - d.T[0]) & (d.B - 1)) / kFoldTile;  // B divides N and 2^32
+        for (uint32_t blk = c0; blk < c0 + 8 && blk < nb; ++blk)
+          tiles.push_back(FoldTile{sig, uint32_t(m), j * d.B + ((blk + shift) % nb) * kFoldTile});
+      }
+    }
+  }
+}
+
+// Orders per-signal fold tiles for the stage launches: union tiles first, by
+// round count, then the one-round tiles, each class in its original order.
+FoldSplit order_for_stages(std::vector<FoldTile>& tiles) {
+  auto cls = [](const FoldTile& t) {
+    const uint32_t nu = fold_tile_rounds(t.m);
+    return nu >= 2 ? nu - 2 : kMaxUnionRounds - 1;
+  };
+  std::stable_sort(tiles.begin(), tiles.end(), [&](const FoldTile& a, const FoldTile& b) { return cls(a) < cls(b); });
+  FoldSplit sp;
+  for (const FoldTile& t : tiles)
+    if (cls(t) < kMaxUnionRounds - 1) ++sp.nunion[cls(t)];
+  return sp;
+}
+
 }  // namespace sfft

@@ -143,6 +143,8 @@ inline int emu_update_dpp(int old, int src, int ctrl, int row_mask, int bank_mas
 #define __builtin_amdgcn_wave_barrier() emu_block->waves[threadIdx.x / 64].bar.wait("wavefront")
 #define __builtin_amdgcn_fence(...) std::atomic_thread_fence(std::memory_order_seq_cst)
 #define __builtin_amdgcn_s_sleep(n) std::this_thread::yield()
+// the kernels apply it to wave-uniform values only, where it is the identity
+#define __builtin_amdgcn_readfirstlane(v) (v)
 
 template <typename T>
 inline T atomicAdd(T* p, T v) {

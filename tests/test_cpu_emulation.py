@@ -48,9 +48,14 @@ FLAVOURS = {
 }
 
 
+# the fold's FP16 storage form needs a host compiler with _Float16: ROCm's clang
+HOST_CLANG = "/opt/rocm/llvm/bin/clang++"
+
+
 def _build(main, flavour):
-    """Builds an emulation program once per source state (host g++, no HIP)."""
-    srcs = [os.path.join(EMU, f) for f in ("recover_emu.cpp", "emu_selftest.cpp", "hip_emu.h", "guarded.h")]
+    """Builds an emulation program once per source state (host compiler, no HIP)."""
+    srcs = [os.path.join(EMU, f) for f in ("recover_emu.cpp", "emu_selftest.cpp", "fold_emu.cpp", "hip_emu.h",
+                                           "guarded.h")]
     srcs += [os.path.join(EMU, "include", "hip", "hip_runtime.h"), os.path.join(CSRC, "plan.cpp"),
              os.path.join(ROOT, "include", "sfft.h")]
     srcs += [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC)) if f.endswith(".h")]
@@ -60,12 +65,12 @@ def _build(main, flavour):
     exe = os.path.join(BUILD, f"{main}_{flavour}_{h.hexdigest()[:16]}")
     if os.path.exists(exe):
         return exe
-    gxx = shutil.which("g++")
-    if not gxx:
-        pytest.skip("g++ not found")
+    gxx = HOST_CLANG if main == "fold_emu" else shutil.which("g++")
+    if not gxx or not os.path.exists(gxx):
+        pytest.skip(f"host compiler for {main} not found")
     os.makedirs(BUILD, exist_ok=True)
     tmp = exe + ".tmp"
-    extra = [os.path.join(CSRC, "plan.cpp")] if main == "recover_emu" else []
+    extra = [os.path.join(CSRC, "plan.cpp")] if main in ("recover_emu", "fold_emu") else []
     subprocess.run([gxx, "-std=c++17", *FLAVOURS[flavour], "-g", "-pthread", "-Wno-unknown-pragmas",
                     "-I", os.path.join(EMU, "include"), "-I", EMU, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
                     os.path.join(EMU, main + ".cpp"), *extra, "-o", tmp], check=True, capture_output=True)
@@ -144,3 +149,31 @@ def test_emulated_recovery_in_bounds_and_exact(tmp_path, case, flavour):
         err = np.linalg.norm(gval - oval) / np.linalg.norm(oval)
         assert err <= tol, err
         assert np.max(np.abs(gval - oval) / np.abs(oval)) <= 10 * tol
+
+
+FOLD_CASES = [
+    # N, K, B, w, loops, l, q, delta, plan seed, dtypes x Kahan
+    (2 ** 14, 40, 512, 7169, 8, 16, "1", 1e-6, 900, [(d, k) for d in (0, 1, 2) for k in (0, 1)]),
+    (2 ** 20, 200, 2048, 40961, 12, 4, "0.25", 1e-6, 61, [(0, 0), (1, 1)]),
+    (2 ** 22, 1000, 2048, 45057, 12, 16, "1", 1e-6, 602, [(0, 0), (2, 0)]),
+]
+
+
+@pytest.mark.parametrize("flavour", sorted(FLAVOURS))
+@pytest.mark.parametrize("case", FOLD_CASES, ids=lambda c: f"N{c[0]}_B{c[2]}_l{c[5]}")
+def test_emulated_fold_union_tiles_bit_exact(case, flavour):
+    """The per-signal fold's union tiles (rounds whose windows overlap round
+    0's, gathered once) give every bucket value bit for bit what one-round
+    tiles give, for 8, 16 and 24 taps in flight, in complex64, complex128
+    and FP16 storage, with and without Kahan summation; every item is
+    written and every access stays inside its buffer (guard pages after,
+    then before, every buffer).  The last case is the metric plan
+    (N = 2^22, B = 2048, w = 45057, 12 iterations)."""
+    exe = _build("fold_emu", flavour)
+    N, K, B, w, M, l, q, delta, seed, forms = case
+    for dtype, kahan in forms:
+        for mode in (0, 1):
+            args = [str(a) for a in (N, K, B, w, M, l, q, delta, seed, dtype, kahan, mode)]
+            r = subprocess.run([exe, *args], capture_output=True, text=True, timeout=300)
+            assert r.returncode == 0, (args, r.returncode, r.stdout[-2000:], r.stderr[-2000:])
+            assert r.stdout.startswith("FOLD OK") and " union 0 " not in r.stdout, r.stdout
