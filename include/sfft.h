@@ -356,7 +356,8 @@ sfft_status sfft_batch_set_tuning(sfft_batch_t b, const sfft_batch_tuning* t);
  * every unroll x wg_per_cu candidate, then the bucket DFT for every
  * fft_group_points candidate, then one whole step of the three stages
  * against the fused launch at four chunk sizes; the fastest step wins.
- * *best receives the fold choice (fold_ms: its mean fold time);
+ * *best receives the fold choice (fold_ms: its mean fold time, as timed when
+ * the choice was made);
  * sfft_batch_get_tuning gives the whole choice.  The choice is kept for the
  * life of the process per batch shape (dtype, Kahan, layout, number of
  * signals and every plan's N, B, w, loops, l and combine): a later call on a

@@ -881,7 +881,11 @@ namespace {
 
 // Choices of the autotuner, per batch shape, for the life of the process.
 std::mutex g_tune_mu;
-std::map<std::string, sfft_batch_tuning> g_tune_cache;
+struct TuneChoice {
+  sfft_batch_tuning tuning;
+  double fold_ms;  // the winning fold shape's mean time when it was chosen
+};
+std::map<std::string, TuneChoice> g_tune_cache;
 
 std::string tuning_key(const sfft_batch_s* b) {
   std::string k = std::to_string(b->dtype) + "/" + std::to_string(b->kahan) + "/" + (b->interleaved ? "pm" : "ps") +
@@ -926,10 +930,10 @@ sfft_status sfft_batch_autotune(sfft_batch_t b, void* stream, sfft_fold_config* 
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto hit = g_tune_cache.find(key);
     if (hit != g_tune_cache.end()) {
-      sfft_status st = sfft_batch_set_tuning(b, &hit->second);
+      sfft_status st = sfft_batch_set_tuning(b, &hit->second.tuning);
       if (st != SFFT_OK) return st;
-      b->step_ms = float(hit->second.step_ms);
-      if (best) *best = sfft_fold_config{b->fold.unroll, b->fold.wg_per_cu, 0.0};
+      b->step_ms = float(hit->second.tuning.step_ms);
+      if (best) *best = sfft_fold_config{b->fold.unroll, b->fold.wg_per_cu, hit->second.fold_ms};
       return SFFT_OK;
     }
   }
@@ -1017,7 +1021,7 @@ sfft_status sfft_batch_autotune(sfft_batch_t b, void* stream, sfft_fold_config* 
   b->step_ms = step;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[key] = tw;
+    g_tune_cache[key] = TuneChoice{tw, double(fold_ms)};
   }
   if (best) *best = sfft_fold_config{win.unroll, win.wg_per_cu, double(fold_ms)};
   return SFFT_OK;
