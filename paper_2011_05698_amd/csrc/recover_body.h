@@ -721,9 +721,15 @@ __device__ void recover_signal(const SignalDesc& sd, RecoverShared<R>& sh) {
   cplx<R>* votes = reinterpret_cast<cplx<R>*>(ws + pd->off_votes);
   uint32_t nrec = 0;
 
+  // The descriptor of iteration m + 1 is read into registers (one word per
+  // thread) while iteration m runs, and stored to LDS when m + 1 starts.
+  constexpr uint32_t kDescWords = uint32_t(sizeof(IterDesc) / 4);
+  static_assert(sizeof(IterDesc) % 4 == 0 && kDescWords <= uint32_t(kRecThreads), "one descriptor word per thread");
+  uint32_t desc_word = tid < kDescWords ? reinterpret_cast<const uint32_t*>(pd->iters)[tid] : 0u;
   for (uint32_t m = 0; m < pd->M; ++m) {
-    copy_words(&sh_it, pd->iters + m, sizeof(IterDesc));
+    if (tid < kDescWords) reinterpret_cast<uint32_t*>(&sh_it)[tid] = desc_word;
     __syncthreads();
+    if (m + 1 < pd->M && tid < kDescWords) desc_word = reinterpret_cast<const uint32_t*>(pd->iters + m + 1)[tid];
     const IterDesc* it = &sh_it;
     const uint32_t B = it->B, L = it->L, D = it->D, R_ = it->R;
     const R* ghat = reinterpret_cast<const R*>(pd->ghat) + it->ghat_off;
@@ -805,26 +811,39 @@ __device__ void recover_signal(const SignalDesc& sd, RecoverShared<R>& sh) {
       for (uint32_t k = tid; k < nst; k += NT) atomicAdd(&cend[raw_u[k] >> cshift], 1u);
       if (subtract) {
         // window weight of each bucket an entry reaches (slot r: bucket
-        // i0(u) + r, i0 = ceil((u - D) / L)), as flat (entry, slot) items
-        const uint32_t ngq = nst * nslot;
-        for (uint32_t q0 = 0; q0 < ngq; q0 += kBatch * NT) {
-          R g[kBatch];
+        // i0(u) + r, i0 = ceil((u - D) / L)), at gw[k * nslot + r]
+        auto weight = [&](uint32_t u, uint32_t r) -> R {
+          const int64_t dist = (first_bucket(u, D, it->logL) + int64_t(r)) * int64_t(L) - int64_t(u);
+          const int64_t ad = dist < 0 ? -dist : dist;
+          return ad <= int64_t(D) ? ghat[ad] : R(0);
+        };
+        if (nslot <= 2) {
+          // both slots of kBatch entries per thread in flight together
+          for (uint32_t k0 = 0; k0 < nst; k0 += kBatch * NT) {
+            R g0[kBatch], g1[kBatch];
 #pragma unroll
-          for (int e = 0; e < kBatch; ++e) {
-            const uint32_t q = q0 + uint32_t(e) * NT + tid;
-            g[e] = R(0);
-            if (q < ngq) {
-              const uint32_t k = q / nslot, r = q - k * nslot;
-              const uint32_t u = raw_u[k];
-              const int64_t dist = (first_bucket(u, D, it->logL) + int64_t(r)) * int64_t(L) - int64_t(u);
-              const int64_t ad = dist < 0 ? -dist : dist;
-              if (ad <= int64_t(D)) g[e] = ghat[ad];
+            for (int e = 0; e < kBatch; ++e) {
+              const uint32_t k = k0 + uint32_t(e) * NT + tid;
+              g0[e] = g1[e] = R(0);
+              if (k < nst) {
+                const uint32_t u = raw_u[k];
+                g0[e] = weight(u, 0);
+                if (nslot == 2) g1[e] = weight(u, 1);
+              }
+            }
+#pragma unroll
+            for (int e = 0; e < kBatch; ++e) {
+              const uint32_t k = k0 + uint32_t(e) * NT + tid;
+              if (k < nst) {
+                gw[k * nslot] = g0[e];
+                if (nslot == 2) gw[k * nslot + 1] = g1[e];
+              }
             }
           }
-#pragma unroll
-          for (int e = 0; e < kBatch; ++e) {
-            const uint32_t q = q0 + uint32_t(e) * NT + tid;
-            if (q < ngq) gw[q] = g[e];
+        } else {
+          for (uint32_t k = tid; k < nst; k += NT) {
+            const uint32_t u = raw_u[k];
+            for (uint32_t r = 0; r < nslot; ++r) gw[k * nslot + r] = weight(u, r);
           }
         }
       }

@@ -69,7 +69,7 @@ def _build(main, flavour):
     if not gxx or not os.path.exists(gxx):
         pytest.skip(f"host compiler for {main} not found")
     os.makedirs(BUILD, exist_ok=True)
-    tmp = exe + ".tmp"
+    tmp = f"{exe}.{os.getpid()}.tmp"  # parallel test workers may build the same program
     extra = [os.path.join(CSRC, "plan.cpp")] if main in ("recover_emu", "fold_emu") else []
     subprocess.run([gxx, "-std=c++17", *FLAVOURS[flavour], "-g", "-pthread", "-Wno-unknown-pragmas",
                     "-I", os.path.join(EMU, "include"), "-I", EMU, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
