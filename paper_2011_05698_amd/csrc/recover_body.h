@@ -34,9 +34,16 @@
 
 namespace sfft {
 
+// Two workgroup shapes run the same code: 256 threads with 77 KiB of LDS
+// (two workgroups per compute unit: batches of more signals than compute
+// units), and 512 threads with 152 KiB (one per compute unit: fewer signals).
+// Every sum over the store is split over lanes the same way in both (team
+// sizes are chosen for 256 threads), so both give the same bits.
 constexpr int kRecThreads = 256;    // 4 waves; the radix select assumes >= 256
+constexpr int kRecThreadsWide = 512;
 constexpr int kWaves = kRecThreads / 64;
 constexpr uint32_t kLdsBytes = kRecoverLdsBytes;
+constexpr uint32_t kLdsBytesWide = 155648;
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr int kRegRounds = 8;       // rounds whose estimates are sorted in registers
 constexpr int kBatch = 4;           // independent loads a thread issues together
@@ -305,6 +312,7 @@ struct Arena {
   unsigned char* glob;
   uint32_t lds_top;
   uint64_t glob_top;
+  uint32_t lds_cap;  // bytes of the LDS buffer
   struct Mark {
     uint32_t l;
     uint64_t g;
@@ -317,7 +325,7 @@ struct Arena {
   template <typename T>
   __device__ T* take(uint64_t count) {
     const uint64_t bytes = (count * sizeof(T) + 15) & ~uint64_t(15);
-    if (uint64_t(lds_top) + bytes <= kLdsBytes) {
+    if (uint64_t(lds_top) + bytes <= lds_cap) {
       T* p = reinterpret_cast<T*>(lds + lds_top);
       lds_top += uint32_t(bytes);
       return p;
@@ -617,10 +625,10 @@ __device__ R loop_median(const cplx<R>* vs, uint32_t n) {
 // round as a binary angle (the location of a failed candidate is never
 // taken, so its angles are not formed).  One thread per candidate, its
 // rounds' values read in batches of kBatch.
-template <typename A, typename R>
+template <typename A, typename R, int NT>
 __device__ void angles_and_consistency(const cplx<R>* y0, const uint16_t* cand, const cplx<R>* rows, uint32_t ncand,
                                        uint32_t R_, bool fp64, R rho, A* th, uint8_t* bad) {
-  for (uint32_t c = threadIdx.x; c < ncand; c += kRecThreads) {
+  for (uint32_t c = threadIdx.x; c < ncand; c += NT) {
     const cplx<R> a = y0[cand[c]];
     const R m0 = sqrt(a.re * a.re + a.im * a.im);
     bool fail = false;
@@ -647,12 +655,12 @@ __device__ void angles_and_consistency(const cplx<R>* y0, const uint16_t* cand, 
   }
 }
 
-template <typename A, typename R>
+template <typename A, typename R, int NT>
 __device__ void locate_candidates(const PlanDesc* pd, const IterDesc* it, const R* ghat, const cplx<R>* y0,
                                   const uint16_t* cand, const cplx<R>* rows, const A* th, const uint8_t* bad,
                                   uint32_t ncand, uint32_t* cu, cplx<R>* cval) {
   const uint32_t nmask = pd->N - 1, logN = pd->logN;
-  for (uint32_t c = threadIdx.x; c < ncand; c += kRecThreads) {
+  for (uint32_t c = threadIdx.x; c < ncand; c += NT) {
     if (bad[c]) continue;
     const uint32_t i = cand[c];
     uint32_t dd = 0;
@@ -670,24 +678,27 @@ __device__ void locate_candidates(const PlanDesc* pd, const IterDesc* it, const 
 
 // LDS state of one signal's recovery.  The fused batch kernel gives its other
 // work items (fold tiles, bucket DFTs) the same buffer.
-template <typename R>
+template <typename R, int NT = kRecThreads, uint32_t LDS = kLdsBytes>
 struct RecoverShared {
-  unsigned char buf[kLdsBytes] __attribute__((aligned(16)));
+  static constexpr int kThreads = NT;
+  static constexpr uint32_t kBuf = LDS;
+  unsigned char buf[LDS] __attribute__((aligned(16)));
   uint32_t hist[2 * 256];
-  uint32_t wsum[kWaves];
+  uint32_t wsum[NT / 64];
   uint32_t sel[2];
   uint32_t nrec;
-  R red[kWaves];
-  typename RealKey<R>::T key[kWaves];
+  R red[NT / 64];
+  typename RealKey<R>::T key[NT / 64];
   // the plan and the current iteration's descriptors, read in every phase
   PlanDesc pd;
   IterDesc it;
 };
 
-// The whole reconstruction of one signal by the calling workgroup
-// (kRecThreads threads).  Everything it keeps in LDS lives in sh.
-template <typename R>
-__device__ void recover_signal(const SignalDesc& sd, RecoverShared<R>& sh) {
+// The whole reconstruction of one signal by the calling workgroup (Sh::kThreads
+// threads).  Everything it keeps in LDS lives in sh.
+template <typename R, typename Sh>
+__device__ void recover_signal(const SignalDesc& sd, Sh& sh) {
+  static_assert(Sh::kThreads >= 256 && Sh::kThreads % 64 == 0, "the radix select and the histograms take 256 threads");
   unsigned char* lds_buf = sh.buf;
   uint32_t* hist = sh.hist;
   uint32_t* wsum = sh.wsum;
@@ -700,10 +711,12 @@ __device__ void recover_signal(const SignalDesc& sd, RecoverShared<R>& sh) {
   using RK = RealKey<R>;
   using KT = typename RK::T;
 
-  const uint32_t tid = threadIdx.x, NT = kRecThreads;
+  const uint32_t tid = threadIdx.x, NT = Sh::kThreads;
   copy_words(&sh_pd, sd.plan, sizeof(PlanDesc));
-  hist[tid] = 0;
-  hist[256 + tid] = 0;
+  if (tid < 256) {
+    hist[tid] = 0;
+    hist[256 + tid] = 0;
+  }
   if (tid == 0) nrec_sh = 0;
   __syncthreads();
   const PlanDesc* pd = &sh_pd;
@@ -724,7 +737,7 @@ __device__ void recover_signal(const SignalDesc& sd, RecoverShared<R>& sh) {
   // The descriptor of iteration m + 1 is read into registers (one word per
   // thread) while iteration m runs, and stored to LDS when m + 1 starts.
   constexpr uint32_t kDescWords = uint32_t(sizeof(IterDesc) / 4);
-  static_assert(sizeof(IterDesc) % 4 == 0 && kDescWords <= uint32_t(kRecThreads), "one descriptor word per thread");
+  static_assert(sizeof(IterDesc) % 4 == 0 && kDescWords <= uint32_t(Sh::kThreads), "one descriptor word per thread");
   uint32_t desc_word = tid < kDescWords ? reinterpret_cast<const uint32_t*>(pd->iters)[tid] : 0u;
   for (uint32_t m = 0; m < pd->M; ++m) {
     if (tid < kDescWords) reinterpret_cast<uint32_t*>(&sh_it)[tid] = desc_word;
@@ -738,7 +751,7 @@ __device__ void recover_signal(const SignalDesc& sd, RecoverShared<R>& sh) {
     const uint32_t nst = nrec;             // store entries when the iteration starts
     const bool subtract = !vote && nst > 0;
     const uint32_t nslot = it->reach + 1;  // buckets a coefficient can reach
-    Arena ar{lds_buf, gwork, 0u, 0ull};
+    Arena ar{lds_buf, gwork, 0u, 0ull, Sh::kBuf};
 
     // ---- 1. the store sorted by permuted frequency, and round 0 ----
     // Cells of the top bits of u hold about one entry each; exact ranks
@@ -770,9 +783,9 @@ __device__ void recover_signal(const SignalDesc& sd, RecoverShared<R>& sh) {
       run = ar.take<RunBounds>(B);
       w0 = ar.take<cplx<R>>(nst);
     }
-    const Arena::Mark mk_det = ar.mark();
+    const auto mk_det = ar.mark();
     KT* pk = ar.take<KT>(B);  // |round 0|^2 as order-preserving keys (detection only)
-    const Arena::Mark mk_tmp = ar.mark();
+    const auto mk_tmp = ar.mark();
     uint32_t* raw_u = nst > 0 ? ar.take<uint32_t>(nst) : nullptr;
     cplx<R>* raw_v = nst > 0 ? ar.take<cplx<R>>(nst) : nullptr;
     uint64_t* tmp = nst > 0 ? ar.take<uint64_t>(nst) : nullptr;
@@ -896,9 +909,10 @@ __device__ void recover_signal(const SignalDesc& sd, RecoverShared<R>& sh) {
       }
       __syncthreads();
       // team size: enough lanes to cover the mean run, as many as let one
-      // pass take all buckets (S B <= NT; at least 1, at most 64)
+      // pass of 256 threads take all buckets (S B <= 256; at least 1, at
+      // most 64): the same in both workgroup shapes
       const double mean_run = double(nst) * double(2 * D + 1) / double(N);
-      while (S < 64 && double(S) < mean_run && S * 2u * B <= 2u * NT) S <<= 1;
+      while (S < 64 && double(S) < mean_run && S * 2u * B <= 2u * uint32_t(kRecThreads)) S <<= 1;
     }
     // The sum over bucket i's run of Ghat x v exp(-2 pi i T_j u / N), by the
     // S lanes of a team: lane-strided partial sums closed by a fixed butterfly.
@@ -1018,7 +1032,7 @@ __device__ void recover_signal(const SignalDesc& sd, RecoverShared<R>& sh) {
     } else {
       const double mean_run = double(nst) * double(2 * D + 1) / double(N);
       uint32_t S2 = 1;
-      while (S2 < 64 && double(S2) < mean_run && S2 * 2u * nitems <= NT) S2 <<= 1;
+      while (S2 < 64 && double(S2) < mean_run && S2 * 2u * nitems <= uint32_t(kRecThreads)) S2 <<= 1;
       const uint32_t team = tid / S2, lane = tid & (S2 - 1), nteams = NT / S2;
       for (uint32_t base_q = 0; base_q < nitems; base_q += nteams) {  // uniform trip count per wave
         const uint32_t q = base_q + team;
@@ -1042,15 +1056,15 @@ __device__ void recover_signal(const SignalDesc& sd, RecoverShared<R>& sh) {
     if (ang32) {
       uint32_t* th = ar.take<uint32_t>(nitems);
       cval = ar.take<cplx<R>>(ncand);
-      angles_and_consistency<uint32_t, R>(y0, cand, rows, ncand, R_, fp64, R(pd->rho), th, bad);
+      angles_and_consistency<uint32_t, R, Sh::kThreads>(y0, cand, rows, ncand, R_, fp64, R(pd->rho), th, bad);
       __syncthreads();
-      locate_candidates<uint32_t, R>(pd, it, ghat, y0, cand, rows, th, bad, ncand, cu, cval);
+      locate_candidates<uint32_t, R, Sh::kThreads>(pd, it, ghat, y0, cand, rows, th, bad, ncand, cu, cval);
     } else {
       uint64_t* th = ar.take<uint64_t>(nitems);
       cval = ar.take<cplx<R>>(ncand);
-      angles_and_consistency<uint64_t, R>(y0, cand, rows, ncand, R_, fp64, R(pd->rho), th, bad);
+      angles_and_consistency<uint64_t, R, Sh::kThreads>(y0, cand, rows, ncand, R_, fp64, R(pd->rho), th, bad);
       __syncthreads();
-      locate_candidates<uint64_t, R>(pd, it, ghat, y0, cand, rows, th, bad, ncand, cu, cval);
+      locate_candidates<uint64_t, R, Sh::kThreads>(pd, it, ghat, y0, cand, rows, th, bad, ncand, cu, cval);
     }
     __syncthreads();
 
@@ -1109,7 +1123,7 @@ __device__ void recover_signal(const SignalDesc& sd, RecoverShared<R>& sh) {
   using TK = TopKey<R>;
   uint32_t npow = 1;
   while (npow < nrec) npow <<= 1;
-  Arena ar{lds_buf, gwork, 0u, 0ull};
+  Arena ar{lds_buf, gwork, 0u, 0ull, Sh::kBuf};
   typename TK::T* tk = ar.take<typename TK::T>(npow);
   uint32_t* tp = ar.take<uint32_t>(npow);  // store entry of each key
   uint32_t nz = 0;

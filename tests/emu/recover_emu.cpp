@@ -1,5 +1,7 @@
 // Runs the recovery kernel body (recover_body.h, the code the GPU kernels
-// run) on the CPU through the emulation layer of hip_emu.h, for one signal
+// run) on the CPU through the emulation layer of hip_emu.h, in both
+// workgroup shapes (256 and 512 threads, which must give the same bits; exit
+// status 4 if they do not), for one signal
 // whose bucket values are given, with every buffer the kernel reads or
 // writes placed against an inaccessible guard page.  An access past the end
 // (guard mode 0) or before the start (guard mode 1) of any buffer stops the
@@ -14,6 +16,7 @@
 // Output file: int64 count, then count entries of (int64 f, double re,
 // double im).
 #include <cstdio>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -94,6 +97,23 @@ int run(HostPlan& hp, const std::vector<double>& y_in, FILE* out) {
   if (c < 0 || c > int64_t(pd->K)) {
     std::fprintf(stderr, "EMU: count %lld outside [0, K]\n", (long long)c);
     return 3;
+  }
+  // the 512-thread shape (twice the LDS) on the same buckets: the same bits
+  using Wide = RecoverShared<R, kRecThreadsWide, kLdsBytesWide>;
+  auto* shw = static_cast<Wide*>(galloc(sizeof(Wide), "workgroup LDS (512 threads)"));
+  auto* idx_w = static_cast<int64_t*>(galloc(sizeof(int64_t) * pd->K, "output frequencies (512 threads)"));
+  auto* val_w = static_cast<cplx<R>*>(galloc(sizeof(cplx<R>) * pd->K, "output values (512 threads)"));
+  auto* count_w = static_cast<int64_t*>(galloc(sizeof(int64_t), "output count (512 threads)"));
+  SignalDesc sdw = sd;
+  sdw.idx = idx_w;
+  sdw.val = val_w;
+  sdw.count = count_w;
+  emu_run_block(kRecThreadsWide, 0, [&] { recover_signal<R>(sdw, *shw); });
+  if (*count_w != c || std::memcmp(idx_w, idx, sizeof(int64_t) * size_t(c)) != 0 ||
+      std::memcmp(static_cast<const void*>(val_w), static_cast<const void*>(val), sizeof(cplx<R>) * size_t(c)) != 0) {
+    std::fprintf(stderr, "EMU: the 512-thread shape differs (count %lld against %lld)\n", (long long)*count_w,
+                 (long long)c);
+    return 4;
   }
   std::fwrite(&c, sizeof c, 1, out);
   for (int64_t k = 0; k < c; ++k) {

@@ -13,9 +13,14 @@ outside a buffer stops the program and names the buffer; a barrier or wave
 move that not every thread reaches is reported as well.  The result must be
 the oracle's support, with values within the GPU tests' tolerance.
 
+The program runs the kernel body in both workgroup shapes (256 threads, and
+512 threads with twice the LDS) and requires the same bits from both; the
+denser N = 2^16 case is one where a team size that followed the shape would
+change them.
+
 The first case is the end-to-end case whose first GPU run, with an earlier
 recovery kernel since replaced, faulted the GPU (complex128, (l, q) =
-(16, 1)); the others are its siblings, a larger shape, and the direct
+(16, 1)); the others are its siblings, larger shapes, and the direct
 location and vote options.
 """
 
@@ -124,6 +129,7 @@ CASES = [
     (2 ** 14, 50, 512, 7169, 8, 16, Fraction(1), 1e-8, "c64", 101, 102, "multiscale", "sum"),
     (2 ** 16, 200, 512, 8193, 10, 16, Fraction(1), 1e-6, "c64", 9, 10, "multiscale", "sum"),
     (2 ** 16, 200, 512, 8193, 10, 16, Fraction(1), 1e-6, "c128", 9, 10, "multiscale", "sum"),
+    (2 ** 16, 400, 1024, 16385, 10, 16, Fraction(1), 1e-6, "c64", 19, 20, "multiscale", "sum"),
     (2 ** 14, 50, 512, 7169, 8, 16, Fraction(1), 1e-6, "c64", 131, 132, "direct", "sum"),
     (2 ** 14, 50, 512, 7169, 8, 16, Fraction(1), 1e-6, "c128", 141, 142, "multiscale", "vote"),
 ]

@@ -402,6 +402,39 @@ def test_vote_metric_shape(sf):
         values_ok(idx[s, :c].cpu().numpy(), val[s, :c].cpu().numpy(), oidx, oval, 1e-4)
 
 
+def test_recovery_shapes_agree(sf):
+    """A batch of more signals than the device has compute units recovers
+    with 256-thread workgroups (two per compute unit); a single execute with
+    a 512-thread workgroup holding twice the LDS.  Both shapes give the same
+    bits.  The shape is the denser N = 2^16, K = 400, B = 1024 plan, where
+    splitting the store sums over a different number of lanes would change
+    them; two signals also match the oracle."""
+    N, K, B, w, M = 2 ** 16, 400, 1024, 16385, 10
+    nsig = torch.cuda.get_device_properties(0).multi_processor_count + 4
+    plan = sf.Plan(N, K, B, w, M, 16, 1.0, delta=1e-6, seed=20)
+    xs, xqs = [], {}
+    for s in range(nsig):
+        x, _, _ = make_signal(SignalSpec(N, K, 19 + s))
+        xd, _, xq = to_dev(x, "c64")
+        xs.append(xd)
+        if s in (0, nsig - 1):
+            xqs[s] = xq
+    batch = sf.Batch([plan] * nsig)
+    idxs, vals, counts = batch.execute(xs)
+    torch.cuda.synchronize()
+    for s in range(nsig):
+        gi, gv, c = run_gpu(sf, plan, xs[s], 1.0)
+        assert int(counts[s].item()) == c, s
+        assert np.array_equal(idxs[s][:c].cpu().numpy(), gi), s
+        assert np.array_equal(vals[s][:c].cpu().numpy(), gv.astype(np.complex64)), s
+    P = O.make_plan(N, K, B, w, M, 16, 1, 1e-6, seed=20)
+    for s, xq in xqs.items():
+        oidx, oval, _ = O.sfft(xq, P)
+        c = int(counts[s].item())
+        values_ok(idxs[s][:c].cpu().numpy(), vals[s][:c].cpu().numpy(), oidx, oval, 1e-4)
+    batch.close()
+
+
 def test_batch_uneven_matches_single(sf):
     """Signals of different N and K in one batch give exactly what single
     executes give, and match the oracle."""
