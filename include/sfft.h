@@ -240,7 +240,10 @@ sfft_status sfft_batch_create(sfft_batch_t* out, const sfft_plan_t* h_plans, int
  * The h_* arrays are host arrays of device pointers.  When they differ from
  * the previous call's, the batch re-uploads its descriptor table with a
  * blocking copy before enqueueing; repeated calls with the same buffers only
- * replay the batch's graph on `stream`.
+ * replay the batch's graph on `stream`.  In the stage launches each signal's
+ * results equal, bit for bit, what sfft_execute gives for it alone: the
+ * launch shapes the library picks by batch size (the recovery's workgroup
+ * size among them) split every sum the same way.
  */
 sfft_status sfft_execute_batch(sfft_batch_t b, const void* const* h_x, const float* h_scale,
                                int64_t* const* h_idx, void* const* h_val, int64_t* d_count, void* stream);
