@@ -655,6 +655,38 @@ def main():
                  "recall_first_8": round(float(np.mean(rec)), 4),
                  "note": "a coefficient that collides in more than half of the loops is dropped"}, ov)
 
+    def metric_variants(steps):
+        """The metric workload at the other plan sizes the workload list names
+        (B = 4096, and B = 16384 by the square-root rule; w = B log2 N | 1) and
+        with 20 dB of noise at B = 2048, position-major, one plan each."""
+        res, keep = {}, {}
+        for tag, Bv, snr in (("B4096", 4096, None), ("B16384", 16384, None), ("snr20", B, 20.0)):
+            wv = (Bv * logN) | 1
+            if snr is None:
+                Xv, XTv, scv = X, XT, scales
+            else:
+                Xn, scv = make_batch(torch, n, N, K, snr, dt, dev, sig_seed)
+                XTv = Xn.transpose(0, 1).contiguous()
+                Xv = None
+                keep_x0 = [host_copy(torch, Xn, s_, dt, scv[s_]) for s_ in (0, 1)]
+                del Xn
+            pv = sfft.Plan(N, K, Bv, wv, M, l, q, delta=delta, seed=plan_seed, dtype=dt)
+            bv = sfft.InterleavedBatch(pv, n)
+            ov = bv.outputs(dev)
+            r = time_batch(bv, lambda: bv.execute(XTv, scales=scv, outs=ov), steps, f"metric {tag}", True)
+            bv.close()
+            res[tag] = {"B": Bv, "w": wv, "snr_db": snr, "layout": "position-major",
+                        "samples_per_signal": pv.samples, "signals_per_s": round(r["value"], 1),
+                        "ms_per_step": round(r["ms_per_step"], 4),
+                        "stage_ms": {"fold": round(r["stage_ms"][0], 4), "bucket_fft": round(r["stage_ms"][1], 4),
+                                     "recover": round(r["stage_ms"][2], 4)},
+                        "tuning_mode": r["tuning"]["mode"]}
+            keep[tag] = (Bv, wv, snr, ov, keep_x0 if snr is not None else None)
+            if snr is not None:
+                del XTv
+                torch.cuda.empty_cache()
+        return res, keep
+
     def plain_form(reps):
         """One signal of the metric workload (signal 0, the same plan), as a
         caller with a single signal runs it: sfft_execute (fold, bucket DFT and
@@ -731,6 +763,8 @@ def main():
     if not args.no_forms and dt == "c64":
         forms["direct_location"] = direct_form(max(2, args.steps // 2))
         forms["vote"], form_outs["vote"] = vote_form(max(2, args.steps // 2))
+    if not args.no_forms and dt == "c64" and args.layout == "position-major":
+        forms["metric_variants"], form_outs["metric_variants"] = metric_variants(max(2, args.steps // 2))
     if not args.no_forms:
         forms["plain"] = plain_form(20)
         forms["independent_plans"], form_outs["independent_plans"] = independent_plans_form(max(2, args.steps // 2))
@@ -788,6 +822,25 @@ def main():
                  "speedup_of_sfft": round(value * dense_s, 3)}
         del Xd
         log(f"dense FFT: {1.0 / dense_s:.1f} signals/s")
+        # the paper compares with a CPU FFT library: a dense FP64 FFT of the
+        # same N on the host, on every core and on one
+        try:
+            import scipy.fft as sfft_cpu
+
+            xc = host_copy(torch, X, 0, dt, scales[0])
+            cpu_fft = {"impl": "scipy.fft.fft, complex128", "host_cpu": host_cpu(),
+                       "note": "its workers split a batch of transforms; one transform of one signal runs on one core"}
+            for label, workers in (("all_cores", os.cpu_count() or 1), ("one_core", 1)):
+                sfft_cpu.fft(xc, workers=workers)
+                t1 = time.perf_counter()
+                for _ in range(3):
+                    sfft_cpu.fft(xc, workers=workers)
+                cpu_fft[label] = {"workers": workers, "signals_per_s": round(3 / (time.perf_counter() - t1), 2)}
+            dense["cpu_fft"] = cpu_fft
+            log(f"dense CPU FFT: {cpu_fft['all_cores']['signals_per_s']} signals/s on "
+                f"{cpu_fft['all_cores']['workers']} workers, {cpu_fft['one_core']['signals_per_s']} on one")
+        except ImportError:
+            pass
 
     # ---- oracle on a bounded sample; parity of that sample ----
     cpu = None
@@ -878,6 +931,26 @@ def main():
             forms["independent_plans"]["parity"] = {"signals_checked": chk, "support_identical": samei,
                                                     "max_rel_l2_identical": worsti,
                                                     "max_per_coefficient_rel_err": worsti_pc}
+
+        if "metric_variants" in form_outs:
+            for tag, (Bv, wv, snr, (iv_, vv_, cv_), xs0) in form_outs["metric_variants"].items():
+                Pm = O.make_plan(N, K, Bv, wv, M, l, Fraction(q), delta, seed=plan_seed)
+                agree, worst_m, worst_pc = [], 0.0, 0.0
+                for s_ in (0, 1):
+                    xh = host_copy(torch, X, s_, dt, scales[s_]) if xs0 is None else xs0[s_]
+                    oi, ov_, _ = O.sfft(xh, Pm)
+                    c = int(cv_[s_].item())
+                    gi, gv = iv_[s_, :c].cpu().numpy(), vv_[s_, :c].cpu().numpy().astype(np.complex128)
+                    common, ga, oa = np.intersect1d(gi, oi, return_indices=True)
+                    agree.append(len(common) / max(len(oi), len(gi), 1))
+                    if len(common):
+                        worst_m = max(worst_m, float(np.linalg.norm(gv[ga] - ov_[oa]) /
+                                                     max(np.linalg.norm(ov_[oa]), 1e-300)))
+                        worst_pc = max(worst_pc, float(np.max(np.abs(gv[ga] - ov_[oa]) /
+                                                              np.maximum(np.abs(ov_[oa]), 1e-300))))
+                forms["metric_variants"][tag]["parity"] = {
+                    "signals_checked": len(agree), "min_support_agreement": round(min(agree), 4),
+                    "max_rel_l2_common": worst_m, "max_per_coefficient_rel_err_common": worst_pc}
 
         if "vote" in form_outs:
             iv, vv, cv = form_outs["vote"]
