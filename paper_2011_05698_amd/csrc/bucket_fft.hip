@@ -32,8 +32,10 @@ __device__ RoundItem load_group(const SigArg& arg, const RoundItem* __restrict__
   return items[grp.first];
 }
 
+constexpr uint32_t kFftLdsMaxThreads = 1024;
+
 template <typename R>
-__global__ __launch_bounds__(256) void bucket_fft_lds_kernel(SigArg arg, const RoundItem* __restrict__ items,
+__global__ __launch_bounds__(kFftLdsMaxThreads) void bucket_fft_lds_kernel(SigArg arg, const RoundItem* __restrict__ items,
                                                              const FftGroup* __restrict__ groups) {
   HIP_DYNAMIC_SHARED(double2, smem_raw)  // 16-byte aligned dynamic LDS
   __shared__ GroupRows<R> rows;
@@ -77,7 +79,10 @@ static int launch_t(const SigArg& sig, const RoundItem* d_items, const FftGroup*
                                                hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
       if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(bucket_fft_lds_kernel<R>, dim3(fg.nlds), dim3(256), lds, s, sig, d_items, d_groups);
+    // a thread per radix-2^2 butterfly group of the largest group's points,
+    // 256 to 1024 threads
+    const uint32_t threads = std::min(kFftLdsMaxThreads, std::max(256u, fg.max_points / 4));
+    hipLaunchKernelGGL(bucket_fft_lds_kernel<R>, dim3(fg.nlds), dim3(threads), lds, s, sig, d_items, d_groups);
   }
   if (fg.ngroups > fg.nlds) {
     // the largest need of the sizes up to the largest present (a smaller B
