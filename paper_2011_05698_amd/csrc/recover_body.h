@@ -18,9 +18,10 @@
 //      |yhat_0|^2): only buckets above it can be detected, so
 //   4. rounds 1..R are formed (bucket values minus their runs) for those
 //      candidate buckets only;
-//   5. per (candidate, round): the phase difference theta_j as a binary angle
-//      and the round-to-round magnitude test;
-//   6. per consistent candidate: location, verification and the median
+//   5. per candidate, the round-to-round magnitude test; the candidates that
+//      pass it form a compact list, and per (listed candidate, round) the
+//      phase difference theta_j as a binary angle;
+//   6. per listed candidate: location, verification and the median
 //      estimate, from values and angles already in LDS;
 //   7. accumulation: a located position is looked up in the sorted store
 //      (no hash index), existing entries are updated, new ones appended.
@@ -621,13 +622,13 @@ __device__ R loop_median(const cplx<R>* vs, uint32_t n) {
 }
 
 // Per candidate: the round-to-round magnitude test of the detection rule
-// over rounds 1..R, then, for a candidate that passes it, theta_j of every
-// round as a binary angle (the location of a failed candidate is never
-// taken, so its angles are not formed).  One thread per candidate, its
-// rounds' values read in batches of kBatch.
-template <typename A, typename R, int NT>
-__device__ void angles_and_consistency(const cplx<R>* y0, const uint16_t* cand, const cplx<R>* rows, uint32_t ncand,
-                                       uint32_t R_, bool fp64, R rho, A* th, uint8_t* bad) {
+// over rounds 1..R.  A candidate that passes it is appended to good (in no
+// particular order: every later step writes per candidate, so the order
+// changes no result); the location of a failed candidate is never taken.
+// One thread per candidate, its rounds' values read in batches of kBatch.
+template <typename R, int NT>
+__device__ void consistency(const cplx<R>* y0, const uint16_t* cand, const cplx<R>* rows, uint32_t ncand, uint32_t R_,
+                            R rho, uint16_t* good, uint32_t* ngood) {
   for (uint32_t c = threadIdx.x; c < ncand; c += NT) {
     const cplx<R> a = y0[cand[c]];
     const R m0 = sqrt(a.re * a.re + a.im * a.im);
@@ -641,8 +642,17 @@ __device__ void angles_and_consistency(const cplx<R>* y0, const uint16_t* cand, 
       for (int e = 0; e < kBatch; ++e)
         if (j0 + uint32_t(e) < R_ && fabs(sqrt(b[e].re * b[e].re + b[e].im * b[e].im) - m0) > rho * m0) fail = true;
     }
-    bad[c] = fail ? 1 : 0;
-    if (fail) continue;
+    if (!fail) good[atomicAdd(ngood, 1u)] = uint16_t(c);
+  }
+}
+
+// theta_j of every round of the candidates that passed, as binary angles.
+template <typename A, typename R, int NT>
+__device__ void angles(const cplx<R>* y0, const uint16_t* cand, const cplx<R>* rows, uint32_t ncand, uint32_t R_,
+                       bool fp64, const uint16_t* good, uint32_t ngood, A* th) {
+  for (uint32_t k = threadIdx.x; k < ngood; k += NT) {
+    const uint32_t c = good[k];
+    const cplx<R> a = y0[cand[c]];
     for (uint32_t j0 = 0; j0 < R_; j0 += kBatch) {
       cplx<R> b[kBatch];
 #pragma unroll
@@ -657,11 +667,11 @@ __device__ void angles_and_consistency(const cplx<R>* y0, const uint16_t* cand, 
 
 template <typename A, typename R, int NT>
 __device__ void locate_candidates(const PlanDesc* pd, const IterDesc* it, const R* ghat, const cplx<R>* y0,
-                                  const uint16_t* cand, const cplx<R>* rows, const A* th, const uint8_t* bad,
-                                  uint32_t ncand, uint32_t* cu, cplx<R>* cval) {
+                                  const uint16_t* cand, const cplx<R>* rows, const A* th, const uint16_t* good,
+                                  uint32_t ngood, uint32_t ncand, uint32_t* cu, cplx<R>* cval) {
   const uint32_t nmask = pd->N - 1, logN = pd->logN;
-  for (uint32_t c = threadIdx.x; c < ncand; c += NT) {
-    if (bad[c]) continue;
+  for (uint32_t k = threadIdx.x; k < ngood; k += NT) {
+    const uint32_t c = good[k];
     const uint32_t i = cand[c];
     uint32_t dd = 0;
     const uint32_t u = locate_bucket<A>(pd, it, i, [&](uint32_t j) { return th[(j - 1) * ncand + c]; }, &dd);
@@ -687,6 +697,7 @@ struct RecoverShared {
   uint32_t wsum[NT / 64];
   uint32_t sel[2];
   uint32_t nrec;
+  uint32_t ngood;  // candidates that passed the round-to-round test
   R red[NT / 64];
   typename RealKey<R>::T key[NT / 64];
   // the plan and the current iteration's descriptors, read in every phase
@@ -1009,7 +1020,8 @@ __device__ void recover_signal(const SignalDesc& sd, Sh& sh) {
         if (p >= thr && p > R(0)) cand[at++] = uint16_t(i);
       }
     }
-    uint8_t* bad = ar.take<uint8_t>(ncand);  // failed the round-to-round test
+    uint16_t* good = ar.take<uint16_t>(ncand);  // candidates that pass the round-to-round test
+    if (tid == 0) sh.ngood = 0;
     cplx<R>* rows = ar.take<cplx<R>>(uint64_t(R_) * ncand);  // round j of candidate c at (j-1) ncand + c
     __syncthreads();
 
@@ -1050,21 +1062,24 @@ __device__ void recover_signal(const SignalDesc& sd, Sh& sh) {
     }
     __syncthreads();
 
-    // ---- 6. phase differences and the round-to-round test ----
+    // ---- 6. the round-to-round test, then phase differences ----
     // ---- 7. location, verification, median estimation ----
     cplx<R>* cval;  // estimates of the located candidates
+    consistency<R, Sh::kThreads>(y0, cand, rows, ncand, R_, R(pd->rho), good, &sh.ngood);
+    __syncthreads();
+    const uint32_t ngood = sh.ngood;
     if (ang32) {
       uint32_t* th = ar.take<uint32_t>(nitems);
       cval = ar.take<cplx<R>>(ncand);
-      angles_and_consistency<uint32_t, R, Sh::kThreads>(y0, cand, rows, ncand, R_, fp64, R(pd->rho), th, bad);
+      angles<uint32_t, R, Sh::kThreads>(y0, cand, rows, ncand, R_, fp64, good, ngood, th);
       __syncthreads();
-      locate_candidates<uint32_t, R, Sh::kThreads>(pd, it, ghat, y0, cand, rows, th, bad, ncand, cu, cval);
+      locate_candidates<uint32_t, R, Sh::kThreads>(pd, it, ghat, y0, cand, rows, th, good, ngood, ncand, cu, cval);
     } else {
       uint64_t* th = ar.take<uint64_t>(nitems);
       cval = ar.take<cplx<R>>(ncand);
-      angles_and_consistency<uint64_t, R, Sh::kThreads>(y0, cand, rows, ncand, R_, fp64, R(pd->rho), th, bad);
+      angles<uint64_t, R, Sh::kThreads>(y0, cand, rows, ncand, R_, fp64, good, ngood, th);
       __syncthreads();
-      locate_candidates<uint64_t, R, Sh::kThreads>(pd, it, ghat, y0, cand, rows, th, bad, ncand, cu, cval);
+      locate_candidates<uint64_t, R, Sh::kThreads>(pd, it, ghat, y0, cand, rows, th, good, ngood, ncand, cu, cval);
     }
     __syncthreads();
 
