@@ -378,9 +378,22 @@ def main():
             run()
         torch.cuda.synchronize()
         graph_ms = (time.perf_counter() - tg) * 1e3 / steps
+        # spread of single graph replays (events on the launch stream), at
+        # least 20 of them
+        reps = max(20, steps)
+        evg = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for e0, e1 in evg:
+            e0.record(stream)
+            run()
+            e1.record(stream)
+        torch.cuda.synchronize()
+        gms = np.array([e0.elapsed_time(e1) for e0, e1 in evg])
+        graph_spread = {"replays": reps, "median_ms": round(float(np.median(gms)), 4),
+                        "p10_ms": round(float(np.quantile(gms, 0.1)), 4), "p90_ms": round(float(np.quantile(gms, 0.9)), 4)}
         nsig = len(batch.plans)
         res = {"value": nsig * steps / elapsed, "ms_per_step": elapsed * 1e3 / steps,
-               "stage_ms": stage_ms, "graph_ms_per_step": graph_ms, "fold_cfg": fold_cfg, "tuning": tuning}
+               "stage_ms": stage_ms, "graph_ms_per_step": graph_ms, "graph_replay_spread": graph_spread,
+               "fold_cfg": fold_cfg, "tuning": tuning}
         if tuning["fused_available"]:  # the other mode, for context
             other = "stages" if fused else "fused"
             batch.set_tuning(mode=other)
@@ -982,6 +995,7 @@ def main():
         "stage_ms": {"fold": round(stage_ms[0], 4), "bucket_fft": round(stage_ms[1], 4),
                      "recover": round(stage_ms[2], 4)},
         "graph_ms_per_step": round(graph_ms, 4),
+        "graph_replay_spread": main_res["graph_replay_spread"],
         # the two other stages against HBM: bucket values read and written once
         # by the bucket DFT, read once by the recovery (its store and outputs
         # are smaller).  Neither reaches the HBM peak: the DFT is bound by the
