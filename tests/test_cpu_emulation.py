@@ -158,10 +158,13 @@ def test_emulated_recovery_in_bounds_and_exact(tmp_path, case, flavour):
 
 
 FOLD_CASES = [
-    # N, K, B, w, loops, l, q, delta, plan seed, dtypes x Kahan
-    (2 ** 14, 40, 512, 7169, 8, 16, "1", 1e-6, 900, [(d, k) for d in (0, 1, 2) for k in (0, 1)]),
-    (2 ** 20, 200, 2048, 40961, 12, 4, "0.25", 1e-6, 61, [(0, 0), (1, 1)]),
-    (2 ** 22, 1000, 2048, 45057, 12, 16, "1", 1e-6, 602, [(0, 0), (2, 0)]),
+    # N, K, B, w, loops, l, q, delta, plan seed, dtypes x Kahan, (tiles, union tiles) or None
+    (2 ** 14, 40, 512, 7169, 8, 16, "1", 1e-6, 900, [(d, k) for d in (0, 1, 2) for k in (0, 1)], None),
+    (2 ** 20, 200, 2048, 40961, 12, 4, "0.25", 1e-6, 61, [(0, 0), (1, 1)], None),
+    # the metric plan: rounds 0..2 of the iterations with B = 2048..256 unite
+    # (offsets 0, tau_1, tau_2 step by less than w; tau_3 - tau_2 > w): 8 + 4
+    # + 2 + 1 union tiles, and the tile count falls from 89 to 59
+    (2 ** 22, 1000, 2048, 45057, 12, 16, "1", 1e-6, 602, [(0, 0), (2, 0)], (59, 15)),
 ]
 
 
@@ -176,10 +179,12 @@ def test_emulated_fold_union_tiles_bit_exact(case, flavour):
     then before, every buffer).  The last case is the metric plan
     (N = 2^22, B = 2048, w = 45057, 12 iterations)."""
     exe = _build("fold_emu", flavour)
-    N, K, B, w, M, l, q, delta, seed, forms = case
+    N, K, B, w, M, l, q, delta, seed, forms, counts = case
     for dtype, kahan in forms:
         for mode in (0, 1):
             args = [str(a) for a in (N, K, B, w, M, l, q, delta, seed, dtype, kahan, mode)]
             r = subprocess.run([exe, *args], capture_output=True, text=True, timeout=300)
             assert r.returncode == 0, (args, r.returncode, r.stdout[-2000:], r.stderr[-2000:])
             assert r.stdout.startswith("FOLD OK") and " union 0 " not in r.stdout, r.stdout
+            if counts:
+                assert f"tiles {counts[0]} union {counts[1]} " in r.stdout, r.stdout
