@@ -169,7 +169,15 @@ void group_rounds(std::vector<RoundItem>& items, BOf b_of, int dtype, std::vecto
     uint32_t c = 1;
     while (a + c < uint32_t(items.size()) && c < cap && b_of(items[a + c]) == B) ++c;
     groups.push_back(FftGroup{a, c});
-    if (logB > wmax) fg.max_points = std::max(fg.max_points, c * B);
+    if (logB > wmax) {
+      // groups come largest B first, so the ones of kFft16Points or more lead
+      if (c * B >= kFft16Points && fg.n16 == uint32_t(groups.size()) - 1) {
+        fg.n16 = uint32_t(groups.size());
+        fg.max_points = std::max(fg.max_points, c * B);
+      } else {
+        fg.max_points_rest = std::max(fg.max_points_rest, c * B);
+      }
+    }
     a += c;
   }
   fg.ngroups = uint32_t(groups.size());

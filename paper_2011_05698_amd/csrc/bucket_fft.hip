@@ -34,18 +34,19 @@ __device__ RoundItem load_group(const SigArg& arg, const RoundItem* __restrict__
 
 constexpr uint32_t kFftLdsMaxThreads = 1024;
 
-template <typename R>
+template <typename R, bool PASS16>
 __global__ __launch_bounds__(kFftLdsMaxThreads) void bucket_fft_lds_kernel(SigArg arg, const RoundItem* __restrict__ items,
-                                                             const FftGroup* __restrict__ groups) {
+                                                                           const FftGroup* __restrict__ groups,
+                                                                           uint32_t first_group) {
   HIP_DYNAMIC_SHARED(double2, smem_raw)  // 16-byte aligned dynamic LDS
   __shared__ GroupRows<R> rows;
-  const FftGroup grp = groups[blockIdx.x];
+  const FftGroup grp = groups[first_group + blockIdx.x];
   const RoundItem first = load_group(arg, items, grp, rows);
   const SignalDesc sd0 = load_signal(arg, first.sig);
   const IterDesc* it0 = sd0.plan->iters + first.m;
   const cplx<R>* tw = reinterpret_cast<const cplx<R>*>(sd0.plan->twiddle) + it0->tw_off;
   __syncthreads();
-  fft_rounds<R>(reinterpret_cast<cplx<R>*>(smem_raw), grp.count, it0->B, it0->logB, tw,
+  fft_rounds<R, PASS16>(reinterpret_cast<cplx<R>*>(smem_raw), grp.count, it0->B, it0->logB, tw,
                 [&](uint32_t g) { return rows.y[g]; }, [&](uint32_t g) { return rows.inv[g]; });
 }
 
@@ -72,17 +73,30 @@ template <typename R>
 static int launch_t(const SigArg& sig, const RoundItem* d_items, const FftGroup* d_groups, const FftGroups& fg,
                     hipStream_t s) {
   constexpr size_t CB = sizeof(cplx<R>);
-  if (fg.nlds) {
-    const size_t lds = size_t(fg.max_points) * CB;
+  // LDS groups [0, n16) hold a sixteen-point butterfly group per thread of
+  // a 1024-thread workgroup and take four stages per pass; the others
+  // [n16, nlds) take two, in a kernel with the registers of that pass alone,
+  // one thread per radix-2^2 butterfly group of the largest group's points
+  // (256 to 1024 threads)
+  const uint32_t bounds[3] = {0u, fg.n16, fg.nlds};
+  for (int k = 0; k < 2; ++k) {
+    const uint32_t g0 = bounds[k], g1 = bounds[k + 1];
+    if (g1 <= g0) continue;
+    const uint32_t pts = k == 0 ? fg.max_points : fg.max_points_rest;
+    const size_t lds = size_t(pts) * CB;
+    const void* fn = k == 0 ? reinterpret_cast<const void*>(&bucket_fft_lds_kernel<R, true>)
+                            : reinterpret_cast<const void*>(&bucket_fft_lds_kernel<R, false>);
     if (lds > 65536) {
-      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&bucket_fft_lds_kernel<R>),
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+      const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
       if (e != hipSuccess) return e;
     }
-    // a thread per radix-2^2 butterfly group of the largest group's points,
-    // 256 to 1024 threads
-    const uint32_t threads = std::min(kFftLdsMaxThreads, std::max(256u, fg.max_points / 4));
-    hipLaunchKernelGGL(bucket_fft_lds_kernel<R>, dim3(fg.nlds), dim3(threads), lds, s, sig, d_items, d_groups);
+    const uint32_t threads = k == 0 ? kFftLdsMaxThreads : std::min(kFftLdsMaxThreads, std::max(256u, pts / 4));
+    if (k == 0)
+      hipLaunchKernelGGL((bucket_fft_lds_kernel<R, true>), dim3(g1 - g0), dim3(threads), lds, s, sig, d_items,
+                         d_groups, g0);
+    else
+      hipLaunchKernelGGL((bucket_fft_lds_kernel<R, false>), dim3(g1 - g0), dim3(threads), lds, s, sig, d_items,
+                         d_groups, g0);
   }
   if (fg.ngroups > fg.nlds) {
     // the largest need of the sizes up to the largest present (a smaller B

@@ -109,10 +109,13 @@ constexpr uint32_t kMaxFftGroupPoints = 4096;  // ... at most (the autotuner's c
 constexpr uint32_t kWaveFftMaxLogB32 = 11, kWaveFftMaxLogB64 = 9;
 constexpr uint32_t kFftWaves = 4;             // waves of a bucket-DFT workgroup
 // The bucket-DFT groups of a plan or batch, largest B first: [0, nlds)
-// take the LDS pass (at most max_points points each), [nlds, ngroups) the
-// wave path (rounds of at most 2^wave_logB points).
+// take the LDS pass, [nlds, ngroups) the wave path (rounds of at most
+// 2^wave_logB points).  Of the LDS groups, [0, n16) hold at least
+// kFft16Points points (at most max_points) and take four radix-2 stages per
+// pass; [n16, nlds) hold fewer (at most max_points_rest).
+constexpr uint32_t kFft16Points = 16384;  // a sixteen-point group per thread of 1024
 struct FftGroups {
-  uint32_t ngroups = 0, nlds = 0, max_points = 0, wave_logB = 0;
+  uint32_t ngroups = 0, nlds = 0, n16 = 0, max_points = 0, max_points_rest = 0, wave_logB = 0;
 };
 
 // ------------------------------------------------------------------ host --
