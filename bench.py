@@ -73,7 +73,7 @@ def make_batch(torch, n, N, K, snr, dtype, dev, seed0):
     return X, scales
 
 
-FOLD_SOURCES = ("fold.hip", "fold_body.h", "device_common.h", "internal.h", "api.hip")
+FOLD_SOURCES = ("fold.hip", "fold_body.h", "device_common.h", "internal.h", "plan.cpp")
 
 
 def measured_traffic(workload_tag):
@@ -92,7 +92,7 @@ def measured_traffic(workload_tag):
         k, v = line.split(None, 1)
         vals[k] = v.strip()
     # the kernel (fold.hip, fold_body.h and the helpers and layout they use)
-    # and the order its tiles are launched in (api.hip)
+    # and the order its tiles are launched in (plan.cpp)
     csrc = os.path.join(ROOT, "paper_2011_05698_amd", "csrc")
     src = b"".join(open(os.path.join(csrc, f), "rb").read() for f in FOLD_SOURCES)
     if vals.get("fold_sources_sha256_16") != hashlib.sha256(src).hexdigest()[:16]:

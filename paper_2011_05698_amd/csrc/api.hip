@@ -561,28 +561,6 @@ sfft_status sfft_recover(sfft_plan_t p, const void* d_yhat, int64_t* d_idx, void
   return SFFT_OK;
 }
 
-// Position-major fold tiles: (iteration, block of kIlvItems items, signal group).
-// Position-major fold tiles, in an order that keeps a gathered row in the
-// L2 of its XCD for the other rounds that need it: bucket b of round 0
-// and bucket b + (T_j - T_0) mod B of round j gather the same residue class
-// of positions, over windows that overlap when tau_j < w, so the tiles of
-// all rounds for one block of round-0 buckets go out together (and, with
-// signal groups innermost, each group keeps to the same XCD when the number
-// of groups is a multiple of 8).  Every (round, bucket block, group) tile
-// appears once.
-void interleaved_tiles(const HostPlan& hp, uint32_t ngroups, std::vector<FoldTile>& tiles) {
-  for (int m = 0; m < hp.loops; ++m) {
-    const IterDesc& d = hp.iters[m].d;
-    const uint32_t nb = d.B / kIlvItems;  // B >= 16 = kIlvItems
-    for (uint32_t blk = 0; blk < nb; ++blk)
-      for (uint32_t j = 0; j <= d.R; ++j) {
-        const uint32_t shift = ((d.T[j] - d.T[0]) & (d.B - 1)) / kIlvItems;  // B divides N and 2^32
-        const uint32_t i0 = j * d.B + ((blk + shift) % nb) * kIlvItems;
-        for (uint32_t g = 0; g < ngroups; ++g) tiles.push_back(FoldTile{g, uint32_t(m), i0});
-      }
-  }
-}
-
 sfft_status create_batch_impl(sfft_batch_t* out, const sfft_plan_t* h_plans, int32_t n, bool interleaved) {
   if (!out || !h_plans || n < 1) return fail(SFFT_ERR_PARAM, "need at least one plan");
   *out = nullptr;

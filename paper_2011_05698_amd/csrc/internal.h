@@ -161,6 +161,8 @@ void build_work_lists(const HostPlan& hp, uint32_t sig, std::vector<FoldTile>& t
 // Orders per-signal fold tiles for the stage launches (FoldSplit) and counts
 // the union tiles of each round count.
 FoldSplit order_for_stages(std::vector<FoldTile>& tiles);
+// The fold tiles of a position-major batch of ngroups signal groups.
+void interleaved_tiles(const HostPlan& hp, uint32_t ngroups, std::vector<FoldTile>& tiles);
 
 // Bytes of the recovery's work area (arrays of one iteration that do not fit
 // in LDS, or the final top-K keys), for any iteration of the plan: every
