@@ -6,9 +6,11 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "internal.h"
@@ -39,6 +41,31 @@ static hipError_t dev_malloc(void** p, size_t bytes) {
   }
   return hipMalloc(p, bytes);
 }
+
+// Device copies of a plan's tables (window, window spectrum, twiddles), in
+// one allocation shared by the plans on the same device and in the same
+// precision whose iterations hold the same host tables (the host plan code
+// gives plans with equal N, L, h and delta one copy of those) and the same
+// B: a batch of plans that differ only in their seeds reads one set of
+// tables.  Freed with the last plan that holds it.  A live entry's host
+// tables are held by the plans that hold the entry, so their addresses
+// cannot be reused while the entry lives.
+struct DevTables {
+  unsigned char* mem = nullptr;
+  ~DevTables() {
+    if (mem) (void)hipFree(mem);
+  }
+};
+struct DevTablesKey {
+  int dev, dtype;
+  std::vector<const void*> tables;  // G and Ghat of each iteration
+  std::vector<uint32_t> B;
+  bool operator<(const DevTablesKey& o) const {
+    return std::tie(dev, dtype, tables, B) < std::tie(o.dev, o.dtype, o.tables, o.B);
+  }
+};
+static std::mutex g_dev_tables_mu;
+static std::map<DevTablesKey, std::weak_ptr<DevTables>> g_dev_tables;
 
 }  // namespace sfft
 
@@ -75,7 +102,8 @@ static void* scratch_address(hipError_t* err) {
 struct sfft_plan_s {
   HostPlan hp;
   bool on_device = false;
-  unsigned char* d_mem = nullptr;   // tables, descriptors, work lists, one-signal workspace
+  unsigned char* d_mem = nullptr;   // descriptors, work lists, one-signal workspace
+  std::shared_ptr<sfft::DevTables> tables;  // window, window spectrum and twiddles (shared)
   PlanDesc* d_plan = nullptr;
   FoldTile* d_tiles = nullptr;
   RoundItem* d_items = nullptr;
@@ -195,8 +223,8 @@ sfft_status upload_plan(sfft_plan_t p) {
   const uint64_t rs = f64 ? 8 : 4;
   uint64_t nwin = 0, nghat = 0, ntw = 0;
   for (auto& it : hp.iters) {
-    nwin += it.G.size();
-    nghat += it.Ghat.size();
+    nwin += it.G->size();
+    nghat += it.Ghat->size();
     ntw += it.d.B / 2;
   }
   std::vector<FoldTile> tiles;
@@ -216,9 +244,6 @@ sfft_status upload_plan(sfft_plan_t p) {
   };
   const uint64_t o_plan = take(sizeof(PlanDesc));
   const uint64_t o_iters = take(sizeof(IterDesc) * hp.iters.size());
-  const uint64_t o_win = take(nwin * rs);
-  const uint64_t o_ghat = take(nghat * rs);
-  const uint64_t o_tw = take(ntw * 2 * rs);
   const uint64_t o_tiles = take(sizeof(FoldTile) * tiles.size());
   const uint64_t o_items = take(sizeof(RoundItem) * items.size());
   const uint64_t o_groups = take(sizeof(FftGroup) * groups.size());
@@ -229,46 +254,87 @@ sfft_status upload_plan(sfft_plan_t p) {
     p->d_mem = nullptr;
     return hip_fail(e, "hipMalloc(plan)");
   }
-  std::vector<unsigned char> host(o_ws, 0);  // everything before the workspace
-  // tables
-  uint64_t wi = 0, gi = 0, ti = 0;
+  // the tables: a live copy of the same ones on this device, or a new one
+  uint64_t toff = 0;
+  auto ttake = [&](uint64_t bytes) {
+    uint64_t o = toff;
+    toff += align256(bytes);
+    return o;
+  };
+  const uint64_t o_win = ttake(nwin * rs);
+  const uint64_t o_ghat = ttake(nghat * rs);
+  const uint64_t o_tw = ttake(ntw * 2 * rs);
+  DevTablesKey key{0, hp.dtype, {}, {}};
+  e = hipGetDevice(&key.dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   for (auto& it : hp.iters) {
-    for (double g : it.G) {
-      if (f64) reinterpret_cast<double*>(host.data() + o_win)[wi++] = g;
-      else reinterpret_cast<float*>(host.data() + o_win)[wi++] = float(g);
+    key.tables.push_back(it.G.get());
+    key.tables.push_back(it.Ghat.get());
+    key.B.push_back(it.d.B);
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_dev_tables_mu);
+    auto hit = g_dev_tables.find(key);
+    if (hit != g_dev_tables.end()) p->tables = hit->second.lock();
+  }
+  if (!p->tables) {
+    auto t = std::make_shared<DevTables>();
+    e = dev_malloc(reinterpret_cast<void**>(&t->mem), toff);
+    if (e != hipSuccess) {
+      t->mem = nullptr;
+      return hip_fail(e, "hipMalloc(plan tables)");
     }
-    for (double g : it.Ghat) {
-      if (f64) reinterpret_cast<double*>(host.data() + o_ghat)[gi++] = g;
-      else reinterpret_cast<float*>(host.data() + o_ghat)[gi++] = float(g);
-    }
-    const uint32_t B = it.d.B;
-    for (uint32_t k = 0; k < B / 2; ++k) {
-      // exp(-2 pi i k / B)
-      const double a = -2.0 * 3.14159265358979323846 * double(k) / double(B);
-      if (f64) {
-        reinterpret_cast<double*>(host.data() + o_tw)[2 * ti] = std::cos(a);
-        reinterpret_cast<double*>(host.data() + o_tw)[2 * ti + 1] = std::sin(a);
-      } else {
-        reinterpret_cast<float*>(host.data() + o_tw)[2 * ti] = float(std::cos(a));
-        reinterpret_cast<float*>(host.data() + o_tw)[2 * ti + 1] = float(std::sin(a));
+    std::vector<unsigned char> th(toff, 0);
+    uint64_t wi = 0, gi = 0, ti = 0;
+    for (auto& it : hp.iters) {
+      for (double g : *it.G) {
+        if (f64) reinterpret_cast<double*>(th.data() + o_win)[wi++] = g;
+        else reinterpret_cast<float*>(th.data() + o_win)[wi++] = float(g);
       }
-      ++ti;
+      for (double g : *it.Ghat) {
+        if (f64) reinterpret_cast<double*>(th.data() + o_ghat)[gi++] = g;
+        else reinterpret_cast<float*>(th.data() + o_ghat)[gi++] = float(g);
+      }
+      const uint32_t B = it.d.B;
+      for (uint32_t k = 0; k < B / 2; ++k) {
+        // exp(-2 pi i k / B)
+        const double a = -2.0 * 3.14159265358979323846 * double(k) / double(B);
+        if (f64) {
+          reinterpret_cast<double*>(th.data() + o_tw)[2 * ti] = std::cos(a);
+          reinterpret_cast<double*>(th.data() + o_tw)[2 * ti + 1] = std::sin(a);
+        } else {
+          reinterpret_cast<float*>(th.data() + o_tw)[2 * ti] = float(std::cos(a));
+          reinterpret_cast<float*>(th.data() + o_tw)[2 * ti + 1] = float(std::sin(a));
+        }
+        ++ti;
+      }
+    }
+    e = hipMemcpy(t->mem, th.data(), toff, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(plan tables)");
+    std::lock_guard<std::mutex> lk(g_dev_tables_mu);
+    auto& slot = g_dev_tables[key];
+    if (auto live = slot.lock()) {
+      p->tables = std::move(live);  // another thread uploaded the same tables first
+    } else {
+      slot = t;
+      p->tables = std::move(t);
     }
   }
+  std::vector<unsigned char> host(o_ws, 0);  // everything before the workspace
   for (size_t m = 0; m < hp.iters.size(); ++m)
     std::memcpy(host.data() + o_iters + m * sizeof(IterDesc), &hp.iters[m].d, sizeof(IterDesc));
   PlanDesc pd = hp.desc;
   pd.iters = reinterpret_cast<const IterDesc*>(p->d_mem + o_iters);
-  pd.window = p->d_mem + o_win;
-  pd.ghat = p->d_mem + o_ghat;
-  pd.twiddle = p->d_mem + o_tw;
+  pd.window = p->tables->mem + o_win;
+  pd.ghat = p->tables->mem + o_ghat;
+  pd.twiddle = p->tables->mem + o_tw;
   hp.desc = pd;
   std::memcpy(host.data() + o_plan, &pd, sizeof(PlanDesc));
   std::memcpy(host.data() + o_tiles, tiles.data(), sizeof(FoldTile) * tiles.size());
   std::memcpy(host.data() + o_items, items.data(), sizeof(RoundItem) * items.size());
   std::memcpy(host.data() + o_groups, groups.data(), sizeof(FftGroup) * groups.size());
   e = hipMemcpy(p->d_mem, host.data(), o_ws, hipMemcpyHostToDevice);
-  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(plan tables)");
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(plan descriptors)");
   p->d_plan = reinterpret_cast<PlanDesc*>(p->d_mem + o_plan);
   p->d_tiles = reinterpret_cast<FoldTile*>(p->d_mem + o_tiles);
   p->d_items = reinterpret_cast<RoundItem*>(p->d_mem + o_items);
@@ -437,7 +503,11 @@ sfft_status sfft_plan(sfft_plan_t* out, int64_t N, int64_t K, int64_t B, int64_t
     return fail(st, err);
   }
   if (!(o.flags & SFFT_PLAN_HOST_ONLY)) {
-    st = upload_plan(p);
+    try {
+      st = upload_plan(p);
+    } catch (const std::bad_alloc&) {
+      st = fail(SFFT_ERR_ALLOC, "host allocation failed while uploading the plan");
+    }
     if (st != SFFT_OK) {
       if (p->d_mem) (void)hipFree(p->d_mem);
       delete p;
@@ -493,8 +563,8 @@ sfft_status sfft_plan_dump_tables(sfft_plan_t p, int32_t m, double* h_window, do
   if (!p) return fail(SFFT_ERR_PARAM, "null plan");
   if (m < 0 || m >= p->hp.loops) return fail(SFFT_ERR_PARAM, "iteration index out of range");
   const IterHost& it = p->hp.iters[m];
-  if (h_window) std::memcpy(h_window, it.G.data(), it.G.size() * sizeof(double));
-  if (h_ghat) std::memcpy(h_ghat, it.Ghat.data(), it.Ghat.size() * sizeof(double));
+  if (h_window) std::memcpy(h_window, it.G->data(), it.G->size() * sizeof(double));
+  if (h_ghat) std::memcpy(h_ghat, it.Ghat->data(), it.Ghat->size() * sizeof(double));
   return SFFT_OK;
 }
 

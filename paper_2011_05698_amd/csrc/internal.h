@@ -3,6 +3,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -122,8 +123,9 @@ struct FftGroups {
 struct IterHost {
   IterDesc d;
   double s_t, s_f, d_delta;
-  std::vector<double> G;          // G_0..G_h
-  std::vector<double> Ghat;       // Ghat_0..Ghat_D
+  // G_0..G_h and Ghat_0..Ghat_D: they depend on N, L, h and delta only, so
+  // plans (and iterations) with the same values share one copy
+  std::shared_ptr<const std::vector<double>> G, Ghat;
   std::vector<uint8_t> kinds;     // 0 block step, 1 enumeration (index 0 unused)
 };
 

@@ -3,8 +3,11 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <thread>
+#include <tuple>
 
 #include "internal.h"
 
@@ -61,28 +64,33 @@ double erfc_inv(double y) {
 // normalisation) of a width-L boxcar whose edge bins weigh 1/2,
 // H_t = sin(pi L t / N) cot(pi t / N), H_0 = L, and g a Gaussian that has
 // fallen to delta at |t| = h.
-void make_window(IterHost& it, int64_t N, double delta) {
-  const int64_t L = it.d.L, h = it.d.h;
-  it.s_t = double(h) / std::sqrt(2.0 * std::log(1.0 / delta));
-  it.G.assign(h + 1, 0.0);
-  it.G[0] = double(L);
+struct Window {
+  double s_t, s_f, d_delta;
+  std::vector<double> G;
+};
+Window make_window(int64_t N, int64_t L, int64_t h, double delta) {
+  Window wd;
+  wd.s_t = double(h) / std::sqrt(2.0 * std::log(1.0 / delta));
+  wd.G.assign(h + 1, 0.0);
+  wd.G[0] = double(L);
   for (int64_t t = 1; t <= h; ++t) {
     int64_t lt = (L * t) % (2 * N);                 // sin(pi L t / N), argument reduced exactly
     double s = std::sin(kPi * double(lt) / double(N));
     double a = kPi * double(t) / double(N);
-    double g = std::exp(-double(t) * double(t) / (2.0 * it.s_t * it.s_t));
-    it.G[t] = s * (std::cos(a) / std::sin(a)) * g;
+    double g = std::exp(-double(t) * double(t) / (2.0 * wd.s_t * wd.s_t));
+    wd.G[t] = s * (std::cos(a) / std::sin(a)) * g;
   }
-  it.s_f = double(N) / (2.0 * kPi * it.s_t);
-  it.d_delta = std::sqrt(2.0) * it.s_f * erfc_inv(2.0 * delta);
+  wd.s_f = double(N) / (2.0 * kPi * wd.s_t);
+  wd.d_delta = std::sqrt(2.0) * wd.s_f * erfc_inv(2.0 * delta);
+  return wd;
 }
 
 // Ghat_k = (1/N) (G_0 + 2 sum_{t=1..h} G_t cos(2 pi (k t mod N) / N)), the
 // DFT of the real, even window, for k = 0..D.  The phase k t mod N is exact;
 // cos(2 pi p / N) comes from two tables (high and low bits of p) joined by
 // the angle-addition formula.  Work is split over k across host threads.
-void make_spectrum(IterHost& it, int64_t N) {
-  const int64_t h = it.d.h, D = it.d.D;
+std::vector<double> make_spectrum(const std::vector<double>& G, int64_t N, int64_t D) {
+  const int64_t h = int64_t(G.size()) - 1;
   const int n = ilog2(uint64_t(N));
   const int lo_bits = n / 2;
   const int64_t nlo = int64_t(1) << lo_bits, nhi = N >> lo_bits;
@@ -97,7 +105,7 @@ void make_spectrum(IterHost& it, int64_t N) {
     clo[i] = std::cos(a);
     slo[i] = std::sin(a);
   }
-  it.Ghat.assign(D + 1, 0.0);
+  std::vector<double> Ghat(D + 1, 0.0);
   const uint64_t mask = uint64_t(N) - 1, lmask = uint64_t(nlo) - 1;
   auto work = [&](int64_t k0, int64_t k1) {
     for (int64_t k = k0; k < k1; ++k) {
@@ -107,16 +115,16 @@ void make_spectrum(IterHost& it, int64_t N) {
         p = (p + uint64_t(k)) & mask;
         uint64_t hi = p >> lo_bits, lo = p & lmask;
         double c = chi[hi] * clo[lo] - shi[hi] * slo[lo];
-        acc += it.G[t] * c;
+        acc += G[t] * c;
       }
-      it.Ghat[k] = (it.G[0] + 2.0 * acc) / double(N);
+      Ghat[k] = (G[0] + 2.0 * acc) / double(N);
     }
   };
   int64_t cost = (D + 1) * h;
   unsigned nt = cost > (int64_t(1) << 22) ? std::max(1u, std::min(16u, std::thread::hardware_concurrency())) : 1u;
   if (nt == 1) {
     work(0, D + 1);
-    return;
+    return Ghat;
   }
   std::vector<std::thread> th;
   int64_t chunk = (D + 1 + nt - 1) / nt;
@@ -125,6 +133,83 @@ void make_spectrum(IterHost& it, int64_t N) {
     if (a < b) th.emplace_back(work, a, b);
   }
   for (auto& t : th) t.join();
+  return Ghat;
+}
+
+// The tables of the live plans, by (N, L, h, delta) for the window and
+// (N, L, h, delta, D) for its spectrum: a plan holds its tables, and a later
+// plan with the same values takes the same copy (tables of plans that are
+// gone are computed again).  Two threads that miss on the same key at once
+// both compute it; the first to insert wins.
+struct TableKey {
+  int64_t N, L, h, D;
+  uint64_t delta_bits;
+  bool operator<(const TableKey& o) const {
+    return std::tie(N, L, h, D, delta_bits) < std::tie(o.N, o.L, o.h, o.D, o.delta_bits);
+  }
+};
+struct WindowEntry {
+  double s_t, s_f, d_delta;
+  std::weak_ptr<const std::vector<double>> G;
+};
+std::mutex g_tables_mu;
+std::map<TableKey, WindowEntry> g_windows;
+std::map<TableKey, std::weak_ptr<const std::vector<double>>> g_spectra;
+
+uint64_t bits_of(double v) {
+  uint64_t b;
+  std::memcpy(&b, &v, sizeof b);
+  return b;
+}
+
+void window_tables(IterHost& it, int64_t N, double delta) {
+  const TableKey key{N, int64_t(it.d.L), int64_t(it.d.h), -1, bits_of(delta)};
+  {
+    std::lock_guard<std::mutex> lk(g_tables_mu);
+    auto hit = g_windows.find(key);
+    if (hit != g_windows.end()) {
+      if (auto G = hit->second.G.lock()) {
+        it.s_t = hit->second.s_t;
+        it.s_f = hit->second.s_f;
+        it.d_delta = hit->second.d_delta;
+        it.G = std::move(G);
+        return;
+      }
+    }
+  }
+  Window wd = make_window(N, it.d.L, it.d.h, delta);
+  auto G = std::make_shared<const std::vector<double>>(std::move(wd.G));
+  std::lock_guard<std::mutex> lk(g_tables_mu);
+  WindowEntry& e = g_windows[key];
+  if (auto live = e.G.lock()) {
+    G = std::move(live);  // another thread inserted it first
+  } else {
+    e = WindowEntry{wd.s_t, wd.s_f, wd.d_delta, G};
+  }
+  it.s_t = e.s_t;
+  it.s_f = e.s_f;
+  it.d_delta = e.d_delta;
+  it.G = std::move(G);
+}
+
+void spectrum_table(IterHost& it, int64_t N, double delta) {
+  const TableKey key{N, int64_t(it.d.L), int64_t(it.d.h), int64_t(it.d.D), bits_of(delta)};
+  {
+    std::lock_guard<std::mutex> lk(g_tables_mu);
+    auto hit = g_spectra.find(key);
+    if (hit != g_spectra.end()) {
+      if (auto S = hit->second.lock()) {
+        it.Ghat = std::move(S);
+        return;
+      }
+    }
+  }
+  auto S = std::make_shared<const std::vector<double>>(make_spectrum(*it.G, N, it.d.D));
+  std::lock_guard<std::mutex> lk(g_tables_mu);
+  auto& e = g_spectra[key];
+  if (auto live = e.lock()) S = std::move(live);
+  else e = S;
+  it.Ghat = std::move(S);
 }
 
 }  // namespace
@@ -190,7 +275,7 @@ sfft_status build_host_plan(HostPlan& hp, int64_t N, int64_t K, int64_t B, int64
     int64_t wm = ((w * Bm) / B) | 1;
     d.B = uint32_t(Bm); d.logB = uint32_t(ilog2(Bm)); d.L = uint32_t(Lm); d.logL = uint32_t(ilog2(Lm));
     d.w = uint32_t(wm); d.h = uint32_t((wm - 1) / 2);
-    make_window(it, N, opt.delta);
+    window_tables(it, N, opt.delta);
     int64_t e = int64_t(std::ceil(it.d_delta));
     if (e > N / 2 - Lm) return bad(SFFT_ERR_PARAM, "window transition wider than the signal allows (w too small for B)");
     d.e = uint32_t(e);
@@ -234,7 +319,7 @@ sfft_status build_host_plan(HostPlan& hp, int64_t N, int64_t K, int64_t B, int64
     d.T[0] = uint32_t(tau0);
     for (int j = 1; j <= R; ++j) d.T[j] = uint32_t((tau0 + d.tau[j]) & nmask);
 
-    make_spectrum(it, N);
+    spectrum_table(it, N, opt.delta);
 
     d.win_off = win_off;  win_off += d.h + 1;
     d.ghat_off = ghat_off; ghat_off += d.D + 1;

@@ -68,12 +68,12 @@ int run(const HostPlan& hp, uint64_t seed) {
   const uint64_t N = uint64_t(hp.N);
   auto* iters = static_cast<IterDesc*>(galloc(sizeof(IterDesc) * M, "iteration descriptors"));
   size_t nwin = 0;
-  for (auto& it : hp.iters) nwin += it.G.size();
+  for (auto& it : hp.iters) nwin += it.G->size();
   auto* win = static_cast<R*>(galloc(nwin * sizeof(R), "window table"));
   size_t wi = 0;
   for (size_t m = 0; m < M; ++m) {
     iters[m] = hp.iters[m].d;
-    for (double g : hp.iters[m].G) win[wi++] = R(g);
+    for (double g : *hp.iters[m].G) win[wi++] = R(g);
   }
   auto* pd = static_cast<PlanDesc*>(galloc(sizeof(PlanDesc), "plan descriptor"));
   *pd = hp.desc;

@@ -52,8 +52,8 @@ int run(HostPlan& hp, const std::vector<double>& y_in, FILE* out) {
   auto* iters = static_cast<IterDesc*>(galloc(sizeof(IterDesc) * M, "iteration descriptors"));
   size_t nwin = 0, nghat = 0, ntw = 0;
   for (auto& it : hp.iters) {
-    nwin += it.G.size();
-    nghat += it.Ghat.size();
+    nwin += it.G->size();
+    nghat += it.Ghat->size();
     ntw += it.d.B / 2;
   }
   auto* win = static_cast<R*>(galloc(nwin * sizeof(R), "window table"));
@@ -62,8 +62,8 @@ int run(HostPlan& hp, const std::vector<double>& y_in, FILE* out) {
   size_t wi = 0, gi = 0;
   for (size_t m = 0; m < M; ++m) {
     iters[m] = hp.iters[m].d;
-    for (double g : hp.iters[m].G) win[wi++] = R(g);
-    for (double g : hp.iters[m].Ghat) ghat[gi++] = R(g);
+    for (double g : *hp.iters[m].G) win[wi++] = R(g);
+    for (double g : *hp.iters[m].Ghat) ghat[gi++] = R(g);
   }
   auto* pd = static_cast<PlanDesc*>(galloc(sizeof(PlanDesc), "plan descriptor"));
   *pd = hp.desc;

@@ -402,6 +402,34 @@ def test_vote_metric_shape(sf):
         values_ok(idx[s, :c].cpu().numpy(), val[s, :c].cpu().numpy(), oidx, oval, 1e-4)
 
 
+def test_plans_share_tables(sf):
+    """Plans that differ only in their seeds share one device copy of the
+    window, window spectrum and twiddle tables.  A plan keeps its results
+    after the plan it shares them with is destroyed and the memory that plan
+    held is reused, and both match the oracle with their own draws."""
+    N, K, B, w, M = 2 ** 14, 40, 512, 7169, 8
+    x, _, _ = make_signal(SignalSpec(N, K, 1000))
+    xd, _, xq = to_dev(x, "c64")
+    pa = sf.Plan(N, K, B, w, M, 16, 1.0, delta=1e-6, seed=900)
+    pb = sf.Plan(N, K, B, w, M, 16, 1.0, delta=1e-6, seed=901)
+    ga = run_gpu(sf, pa, xd, 1.0)
+    gb = run_gpu(sf, pb, xd, 1.0)
+    pa.close()
+    junk = torch.full((64 << 20,), 7.0, dtype=torch.float32, device=DEV)  # reuses freed memory
+    torch.cuda.synchronize()
+    gb2 = run_gpu(sf, pb, xd, 1.0)
+    del junk
+    assert np.array_equal(gb2[0], gb[0]) and np.array_equal(gb2[1], gb[1])
+    for seed, (gi, gv, _) in ((900, ga), (901, gb2)):
+        oidx, oval, _ = O.sfft(xq, O.make_plan(N, K, B, w, M, 16, 1, 1e-6, seed=seed))
+        values_ok(gi, gv, oidx, oval, 1e-4)
+    pc = sf.Plan(N, K, B, w, M, 16, 1.0, delta=1e-6, seed=900)  # a new plan of the first draw
+    gc = run_gpu(sf, pc, xd, 1.0)
+    assert np.array_equal(gc[0], ga[0]) and np.array_equal(gc[1], ga[1])
+    pb.close()
+    pc.close()
+
+
 def test_recovery_shapes_agree(sf):
     """A batch of more signals than the device has compute units recovers
     with 256-thread workgroups (two per compute unit); a single execute with
