@@ -12,8 +12,11 @@
  *   - Every call returns sfft_status; nothing throws across the ABI.
  *   - Pointers named d_* are device (HIP) pointers owned by the caller;
  *     h_* are host pointers owned by the caller.  The library never frees a
- *     caller's buffer.  Plans and batches own their device tables and
- *     workspace and free them in sfft_destroy / sfft_batch_destroy.
+ *     caller's buffer.  Plans and batches own their workspace and free it in
+ *     sfft_destroy / sfft_batch_destroy.  A plan's read-only tables (window,
+ *     window spectrum, twiddles) are shared with the other live plans of the
+ *     same N, B, w, loops, delta and dtype on the same device, and freed with
+ *     the last of them.
  *   - Execute calls are asynchronous and stream-ordered on `stream` (a
  *     hipStream_t; NULL is the default stream).  Outputs are valid once the
  *     stream has been synchronised.  At most one execute may be in flight
@@ -128,7 +131,8 @@ void sfft_default_options(sfft_options* opt);
  * Limits (SFFT_ERR_UNSUPPORTED): B <= 16384 for SFFT_C64/SFFT_F16X2_SCALED,
  * B <= 8192 for SFFT_C128 (the bucket DFT keeps B values in 128 KiB of LDS);
  * at most 47 location steps per iteration.
- * On success *out holds a plan owning its tables and workspace.
+ * On success *out holds a plan owning its workspace and holding its tables
+ * (shared with the live plans that need the same ones).
  */
 sfft_status sfft_plan(sfft_plan_t* out, int64_t N, int64_t K, int64_t B, int64_t w, int32_t loops,
                       int32_t multiscale, double extension, const sfft_options* opt);
