@@ -312,6 +312,8 @@ sfft_status upload_plan(sfft_plan_t p) {
     e = hipMemcpy(t->mem, th.data(), toff, hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpy(plan tables)");
     std::lock_guard<std::mutex> lk(g_dev_tables_mu);
+    for (auto i = g_dev_tables.begin(); i != g_dev_tables.end();)  // entries of tables no plan holds
+      i = i->second.expired() ? g_dev_tables.erase(i) : std::next(i);
     auto& slot = g_dev_tables[key];
     if (auto live = slot.lock()) {
       p->tables = std::move(live);  // another thread uploaded the same tables first

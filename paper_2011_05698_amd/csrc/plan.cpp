@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <iterator>
 #include <map>
 #include <mutex>
 #include <new>
@@ -180,6 +181,8 @@ void window_tables(IterHost& it, int64_t N, double delta) {
   Window wd = make_window(N, it.d.L, it.d.h, delta);
   auto G = std::make_shared<const std::vector<double>>(std::move(wd.G));
   std::lock_guard<std::mutex> lk(g_tables_mu);
+  for (auto i = g_windows.begin(); i != g_windows.end();)  // entries of tables no plan holds
+    i = i->second.G.expired() ? g_windows.erase(i) : std::next(i);
   WindowEntry& e = g_windows[key];
   if (auto live = e.G.lock()) {
     G = std::move(live);  // another thread inserted it first
@@ -206,6 +209,8 @@ void spectrum_table(IterHost& it, int64_t N, double delta) {
   }
   auto S = std::make_shared<const std::vector<double>>(make_spectrum(*it.G, N, it.d.D));
   std::lock_guard<std::mutex> lk(g_tables_mu);
+  for (auto i = g_spectra.begin(); i != g_spectra.end();)
+    i = i->second.expired() ? g_spectra.erase(i) : std::next(i);
   auto& e = g_spectra[key];
   if (auto live = e.lock()) S = std::move(live);
   else e = S;
