@@ -670,10 +670,12 @@ def main():
 
     def metric_variants(steps):
         """The metric workload at the other plan sizes the workload list names
-        (B = 4096, and B = 16384 by the square-root rule; w = B log2 N | 1) and
-        with 20 dB of noise at B = 2048, position-major, one plan each."""
+        (B = 4096, and B = 16384 by the square-root rule; w = B log2 N | 1),
+        with 20 dB of noise at B = 2048, and with the compensated (Kahan) fold,
+        position-major, one plan each."""
         res, keep = {}, {}
-        for tag, Bv, snr in (("B4096", 4096, None), ("B16384", 16384, None), ("snr20", B, 20.0)):
+        for tag, Bv, snr, kahan in (("B4096", 4096, None, False), ("B16384", 16384, None, False),
+                                    ("snr20", B, 20.0, False), ("kahan", B, None, True)):
             wv = (Bv * logN) | 1
             if snr is None:
                 Xv, XTv, scv = X, XT, scales
@@ -683,12 +685,12 @@ def main():
                 Xv = None
                 keep_x0 = [host_copy(torch, Xn, s_, dt, scv[s_]) for s_ in (0, 1)]
                 del Xn
-            pv = sfft.Plan(N, K, Bv, wv, M, l, q, delta=delta, seed=plan_seed, dtype=dt)
+            pv = sfft.Plan(N, K, Bv, wv, M, l, q, delta=delta, seed=plan_seed, dtype=dt, kahan=kahan)
             bv = sfft.InterleavedBatch(pv, n)
             ov = bv.outputs(dev)
             r = time_batch(bv, lambda: bv.execute(XTv, scales=scv, outs=ov), steps, f"metric {tag}", True)
             bv.close()
-            res[tag] = {"B": Bv, "w": wv, "snr_db": snr, "layout": "position-major",
+            res[tag] = {"B": Bv, "w": wv, "snr_db": snr, "kahan": kahan, "layout": "position-major",
                         "samples_per_signal": pv.samples, "signals_per_s": round(r["value"], 1),
                         "ms_per_step": round(r["ms_per_step"], 4),
                         "stage_ms": {"fold": round(r["stage_ms"][0], 4), "bucket_fft": round(r["stage_ms"][1], 4),
