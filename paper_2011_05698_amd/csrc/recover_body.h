@@ -697,6 +697,7 @@ struct RecoverShared {
   uint32_t wsum[NT / 64];
   uint32_t sel[2];
   uint32_t nrec;
+  uint32_t ncand;  // candidate buckets of the iteration
   uint32_t ngood;  // candidates that passed the round-to-round test
   R red[NT / 64];
   typename RealKey<R>::T key[NT / 64];
@@ -997,33 +998,24 @@ __device__ void recover_signal(const SignalDesc& sd, Sh& sh) {
     const R thr_noise = R(2.0 * it->log_B) * (med / R(0.69314718055994530942));
     const R thr_floor = R(pd->eta * pd->eta) * mx;
     const R thr = thr_noise > thr_floor ? thr_noise : thr_floor;
+    if (tid == 0) sh.ncand = 0;
     __syncthreads();  // sh_key is read before it is written again
     ar.release(mk_det);
 
-    // ---- 4. candidate buckets (above the threshold), in bucket order ----
-    uint32_t ncand;
-    uint16_t* cand;  // bucket indices (B <= 16384)
-    {
-      const uint32_t chunk = (B + NT - 1) / NT;
-      const uint32_t lo = min(B, tid * chunk), hi = min(B, lo + chunk);
-      uint32_t mine = 0;
-      for (uint32_t i = lo; i < hi; ++i) {
-        const cplx<R> v = y0[i];
-        const R p = v.re * v.re + v.im * v.im;
-        mine += (p >= thr && p > R(0)) ? 1u : 0u;
-      }
-      uint32_t at = block_excl_scan(mine, wsum, &ncand);
-      cand = ar.take<uint16_t>(ncand);
-      for (uint32_t i = lo; i < hi; ++i) {
-        const cplx<R> v = y0[i];
-        const R p = v.re * v.re + v.im * v.im;
-        if (p >= thr && p > R(0)) cand[at++] = uint16_t(i);
-      }
+    // ---- 4. candidate buckets (above the threshold), appended in no
+    // particular order: every later step writes per candidate, so the order
+    // changes no result ----
+    uint16_t* cand = ar.take<uint16_t>(B);  // bucket indices (B <= 16384)
+    for (uint32_t i = tid; i < B; i += NT) {
+      const cplx<R> v = y0[i];
+      const R p = v.re * v.re + v.im * v.im;
+      if (p >= thr && p > R(0)) cand[atomicAdd(&sh.ncand, 1u)] = uint16_t(i);
     }
-    uint16_t* good = ar.take<uint16_t>(ncand);  // candidates that pass the round-to-round test
-    if (tid == 0) sh.ngood = 0;
-    cplx<R>* rows = ar.take<cplx<R>>(uint64_t(R_) * ncand);  // round j of candidate c at (j-1) ncand + c
     __syncthreads();
+    const uint32_t ncand = sh.ncand;
+    uint16_t* good = ar.take<uint16_t>(ncand);  // candidates that pass the round-to-round test
+    if (tid == 0) sh.ngood = 0;  // read after the barrier that ends step 5
+    cplx<R>* rows = ar.take<cplx<R>>(uint64_t(R_) * ncand);  // round j of candidate c at (j-1) ncand + c
 
     // ---- 5. rounds 1..R of the candidates, minus the store's contributions ----
     const uint32_t nitems = R_ * ncand;
