@@ -99,7 +99,12 @@ def measured_traffic(workload_tag):
         return None, "fold kernel or its launch order changed since the counters were taken"
     # the launch shape moves no bytes (every shape gathers the same samples), so
     # counters taken at another unroll or cap still price this launch
-    return int(float(vals["fold_hbm_bytes_per_launch"])), os.path.relpath(path, ROOT)
+    # position-major: one fold launch per step; per-signal: the union-tile and
+    # one-round launches of one step together
+    nbytes = vals.get("fold_hbm_bytes_per_launch", vals.get("fold_hbm_bytes_per_step"))
+    if nbytes is None:
+        return None, f"{os.path.relpath(path, ROOT)} holds no fold byte count"
+    return int(float(nbytes)), os.path.relpath(path, ROOT)
 
 
 def experiments(torch, sfft, dev):
@@ -802,7 +807,8 @@ def main():
     lay = "posmajor" if args.layout == "position-major" else "persignal"
     tag = f"metric_batch{n}_{dt}_{lay}" if (N, K, B, M, args.snr) == (2 ** 22, 1000, 2048, 12, None) else None
     traffic, source = measured_traffic(tag) if tag else (None, None)
-    fold_kernel = "fold_interleaved_kernel" if args.layout == "position-major" else "fold_kernel"
+    fold_kernel = ("fold_interleaved_kernel" if args.layout == "position-major"
+                   else "fold_union_kernel + fold_kernel (the fold stage's two launches)")
     if main_res["tuning"]["mode"] == "fused":  # one kernel per step: price the whole step's gathers on it
         fold_kernel, traffic, source = "fused_kernel", None, "the fused launch: counters not taken"
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
