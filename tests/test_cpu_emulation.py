@@ -51,6 +51,10 @@ FLAVOURS = {
     "plain": ["-O2"],
     "fma": ["-O2", "-mfma", "-ffp-contract=fast"],
 }
+# host AddressSanitizer and UndefinedBehaviorSanitizer: every thread's
+# private arrays (the kernel's registers and scratch) are host stack arrays,
+# which the guard pages do not cover and these do
+SANITIZED = ["-O1", "-g", "-fsanitize=address,undefined", "-fno-omit-frame-pointer"]
 
 
 # the fold's FP16 storage form needs a host compiler with _Float16: ROCm's clang
@@ -64,7 +68,8 @@ def _build(main, flavour):
     srcs += [os.path.join(EMU, "include", "hip", "hip_runtime.h"), os.path.join(CSRC, "plan.cpp"),
              os.path.join(ROOT, "include", "sfft.h")]
     srcs += [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC)) if f.endswith(".h")]
-    h = hashlib.sha256(" ".join(FLAVOURS[flavour]).encode())
+    flags = SANITIZED if flavour == "sanitized" else FLAVOURS[flavour]
+    h = hashlib.sha256(" ".join(flags).encode())
     for f in srcs:
         h.update(open(f, "rb").read())
     exe = os.path.join(BUILD, f"{main}_{flavour}_{h.hexdigest()[:16]}")
@@ -76,7 +81,7 @@ def _build(main, flavour):
     os.makedirs(BUILD, exist_ok=True)
     tmp = f"{exe}.{os.getpid()}.tmp"  # parallel test workers may build the same program
     extra = [os.path.join(CSRC, "plan.cpp")] if main in ("recover_emu", "fold_emu") else []
-    subprocess.run([gxx, "-std=c++17", *FLAVOURS[flavour], "-g", "-pthread", "-Wno-unknown-pragmas",
+    subprocess.run([gxx, "-std=c++17", *flags, "-g", "-pthread", "-Wno-unknown-pragmas",
                     "-I", os.path.join(EMU, "include"), "-I", EMU, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
                     os.path.join(EMU, main + ".cpp"), *extra, "-o", tmp], check=True, capture_output=True)
     os.replace(tmp, exe)
@@ -106,7 +111,8 @@ def oracle_buckets(x, P):
                            for it in P.iters])
 
 
-def run_emulated(tmp_path, y, N, K, B, w, M, l, q, delta, seed, dtype, guard_mode, flavour, location=0, combine=0):
+def run_emulated(tmp_path, y, N, K, B, w, M, l, q, delta, seed, dtype, guard_mode, flavour, location=0, combine=0,
+                 env=None):
     exe = _build("recover_emu", flavour)
     inp, out = tmp_path / f"in{guard_mode}.bin", tmp_path / f"out{guard_mode}_{flavour}.bin"
     y = np.asarray(y, dtype=np.complex128)
@@ -114,7 +120,7 @@ def run_emulated(tmp_path, y, N, K, B, w, M, l, q, delta, seed, dtype, guard_mod
         f.write(struct.pack("<qqqqiiddQiiiiq", N, K, B, w, M, l, float(q), delta, seed, DTYPES[dtype], location,
                             combine, guard_mode, len(y)))
         f.write(np.stack([y.real, y.imag], axis=1).astype("<f8").tobytes())
-    r = subprocess.run([exe, str(inp), str(out)], capture_output=True, text=True, timeout=600)
+    r = subprocess.run([exe, str(inp), str(out)], capture_output=True, text=True, timeout=900, env=env)
     assert r.returncode == 0, f"exit {r.returncode}: {r.stdout[-2000:]} {r.stderr[-2000:]}"
     data = open(out, "rb").read()
     c = struct.unpack_from("<q", data)[0]
@@ -188,3 +194,24 @@ def test_emulated_fold_union_tiles_bit_exact(case, flavour):
             assert r.stdout.startswith("FOLD OK") and " union 0 " not in r.stdout, r.stdout
             if counts:
                 assert f"tiles {counts[0]} union {counts[1]} " in r.stdout, r.stdout
+
+
+def test_emulated_recovery_sanitized(tmp_path):
+    """The case whose first GPU run, with an earlier recovery kernel, faulted
+    the GPU (complex128, (l, q) = (16, 1), N = 2^14, K = 50, delta = 1e-8,
+    plan seed 102), through the current kernel body built with host
+    AddressSanitizer and UndefinedBehaviorSanitizer on top of the guard
+    pages: no access outside any array (private ones included) and no
+    undefined behaviour, in both workgroup shapes and both guard modes, and
+    the oracle's support and values."""
+    N, K, B, w, M, l, q, delta, dt, ss, ps, loc, comb = CASES[0]
+    x, sup, _ = make_signal(SignalSpec(N, K, ss))
+    P = O.make_plan(N, K, B, w, M, l, q, delta, seed=ps)
+    y = oracle_buckets(x, P)
+    oidx, oval, _ = O.sfft(x, P)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:exitcode=97:detect_stack_use_after_return=1",
+               UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
+    for mode in (0, 1):
+        gidx, gval = run_emulated(tmp_path, y, N, K, B, w, M, l, q, delta, ps, dt, mode, "sanitized", env=env)
+        assert np.array_equal(gidx, oidx)
+        assert np.linalg.norm(gval - oval) / np.linalg.norm(oval) <= 1e-10
