@@ -430,7 +430,8 @@ def test_plans_share_tables(sf):
     pc.close()
 
 
-def test_recovery_shapes_agree(sf):
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+def test_recovery_shapes_agree(sf, dt):
     """A batch of more signals than the device has compute units recovers
     with 256-thread workgroups (two per compute unit); a single execute with
     a 512-thread workgroup holding twice the LDS.  Both shapes give the same
@@ -439,11 +440,11 @@ def test_recovery_shapes_agree(sf):
     them; two signals also match the oracle."""
     N, K, B, w, M = 2 ** 16, 400, 1024, 16385, 10
     nsig = torch.cuda.get_device_properties(0).multi_processor_count + 4
-    plan = sf.Plan(N, K, B, w, M, 16, 1.0, delta=1e-6, seed=20)
+    plan = sf.Plan(N, K, B, w, M, 16, 1.0, delta=1e-6, seed=20, dtype=dt)
     xs, xqs = [], {}
     for s in range(nsig):
         x, _, _ = make_signal(SignalSpec(N, K, 19 + s))
-        xd, _, xq = to_dev(x, "c64")
+        xd, _, xq = to_dev(x, dt)
         xs.append(xd)
         if s in (0, nsig - 1):
             xqs[s] = xq
@@ -454,12 +455,12 @@ def test_recovery_shapes_agree(sf):
         gi, gv, c = run_gpu(sf, plan, xs[s], 1.0)
         assert int(counts[s].item()) == c, s
         assert np.array_equal(idxs[s][:c].cpu().numpy(), gi), s
-        assert np.array_equal(vals[s][:c].cpu().numpy(), gv.astype(np.complex64)), s
+        assert np.array_equal(vals[s][:c].cpu().numpy().astype(np.complex128), gv), s
     P = O.make_plan(N, K, B, w, M, 16, 1, 1e-6, seed=20)
     for s, xq in xqs.items():
         oidx, oval, _ = O.sfft(xq, P)
         c = int(counts[s].item())
-        values_ok(idxs[s][:c].cpu().numpy(), vals[s][:c].cpu().numpy(), oidx, oval, 1e-4)
+        values_ok(idxs[s][:c].cpu().numpy(), vals[s][:c].cpu().numpy(), oidx, oval, 1e-10 if dt == "c128" else 1e-4)
     batch.close()
 
 
