@@ -138,6 +138,7 @@ struct sfft_batch_s {
   FoldConfig fold{8, 0};
   bool interleaved = false;         // one plan, position-major signals (sfft_batch_create_interleaved)
   uint32_t ngroups = 0;             // interleaved: signal groups of kIlvSigs
+  bool pairs_ok = false;            // interleaved: the bound input can take two signals per fold lane
   // bucket-DFT grouping: round items (host copy) cut into groups of at most fft_group_points points
   std::vector<RoundItem> h_items;
   uint32_t fft_group_points = kFftGroupPoints;
@@ -445,8 +446,8 @@ sfft_status regroup_fft(sfft_batch_s* b, uint32_t points) {
 
 int launch_batch_fold(const sfft_batch_s* b, const FoldConfig& cfg, hipStream_t s) {
   if (b->interleaved)
-    return launch_fold_interleaved(b->dtype, b->kahan, cfg.unroll, b->d_sigs, uint32_t(b->plans.size()), b->d_tiles,
-                                   b->ntiles, s);
+    return launch_fold_interleaved(b->dtype, b->kahan, cfg.unroll, b->pairs_ok && cfg.pairs, b->d_sigs,
+                                   uint32_t(b->plans.size()), b->d_tiles, b->ntiles, s);
   return launch_fold(b->dtype, b->kahan, cfg, table_arg(b), b->d_tiles, b->ntiles, b->split, s);
 }
 
@@ -820,6 +821,8 @@ sfft_status sfft_batch_create_interleaved(sfft_batch_t* out, sfft_plan_t plan, i
   return create_batch(out, plans.data(), nsig, true);
 }
 
+static sfft_status drop_graph(sfft_batch_t b);
+
 sfft_status sfft_execute_interleaved(sfft_batch_t b, const void* d_x, int64_t ld, const float* h_scale,
                                      int64_t* d_idx, void* d_val, int64_t* d_count, void* stream) {
   if (!b || !d_x || !d_idx || !d_val || !d_count) return fail(SFFT_ERR_PARAM, "null argument");
@@ -842,6 +845,16 @@ sfft_status sfft_execute_interleaved(sfft_batch_t b, const void* d_x, int64_t ld
     sd.count = d_count + i;
     sd.scale = h_scale ? h_scale[i] : 1.0f;
     sd.ld = uint32_t(ld);
+  }
+  // two signals per fold lane where each lane's pair is one aligned load of
+  // two live signals (and the fold shape takes them); a change either way
+  // captures the graph again
+  const bool pairs_ok = b->dtype != SFFT_C128 && b->ngroups % 2 == 0 && n % 2 == 0 && ld % 2 == 0 &&
+                        reinterpret_cast<uintptr_t>(d_x) % (2 * es) == 0;
+  if (pairs_ok != b->pairs_ok) {
+    const sfft_status st = drop_graph(b);
+    if (st != SFFT_OK) return st;
+    b->pairs_ok = pairs_ok;
   }
   return bind_and_replay(b, sig, reinterpret_cast<hipStream_t>(stream));
 }
@@ -887,7 +900,7 @@ sfft_status sfft_plan_set_fold_config(sfft_plan_t p, const sfft_fold_config* cfg
 
 sfft_status sfft_batch_set_fold_config(sfft_batch_t b, const sfft_fold_config* cfg) {
   if (!b || !valid_fold(cfg)) return fail(SFFT_ERR_PARAM, "invalid fold configuration");
-  b->fold = FoldConfig{cfg->unroll, cfg->wg_per_cu};
+  b->fold = FoldConfig{cfg->unroll, cfg->wg_per_cu, b->fold.pairs};
   return drop_graph(b);
 }
 
@@ -929,7 +942,7 @@ sfft_status sfft_batch_set_tuning(sfft_batch_t b, const sfft_batch_tuning* t) {
     b->fused_chunk = uint32_t(t->fused_chunk);
   }
   b->mode = t->mode;
-  b->fold = FoldConfig{t->fold_unroll, t->fold_wg_per_cu};
+  b->fold = FoldConfig{t->fold_unroll, t->fold_wg_per_cu, b->fold.pairs};
   return SFFT_OK;
 }
 
@@ -942,11 +955,12 @@ std::mutex g_tune_mu;
 struct TuneChoice {
   sfft_batch_tuning tuning;
   double fold_ms;  // the winning fold shape's mean time when it was chosen
+  bool fold_pairs; // position-major: two signals per fold lane
 };
 std::map<std::string, TuneChoice> g_tune_cache;
 
 std::string tuning_key(const sfft_batch_s* b) {
-  std::string k = std::to_string(b->dtype) + "/" + std::to_string(b->kahan) + "/" + (b->interleaved ? "pm" : "ps") +
+  std::string k = std::to_string(b->dtype) + "/" + std::to_string(b->kahan) + "/" + (b->interleaved ? (b->pairs_ok ? "pm2" : "pm") : "ps") +
                   "/" + std::to_string(b->plans.size());
   uint64_t h = 1469598103934665603ull;  // FNV-1a over every plan's shape
   for (const sfft_plan_t p : b->plans) {
@@ -988,6 +1002,7 @@ sfft_status sfft_batch_autotune(sfft_batch_t b, void* stream, sfft_fold_config* 
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto hit = g_tune_cache.find(key);
     if (hit != g_tune_cache.end()) {
+      b->fold.pairs = hit->second.fold_pairs;
       sfft_status st = sfft_batch_set_tuning(b, &hit->second.tuning);
       if (st != SFFT_OK) return st;
       b->step_ms = float(hit->second.tuning.step_ms);
@@ -1002,15 +1017,16 @@ sfft_status sfft_batch_autotune(sfft_batch_t b, void* stream, sfft_fold_config* 
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return fail(SFFT_ERR_LAUNCH, "hipEventCreate");
   int err = hipSuccess;
   const SigArg a = table_arg(b);
-  // 1. fold launch shape: taps in flight x residency cap (per-signal layout only)
+  // 1. fold launch shape: taps in flight x residency cap (per-signal layout)
+  //    or x signals per lane (position-major, where the input allows two)
   const int unrolls[3] = {8, 16, 24};
   const int caps[5] = {0, 2, 3, 4, 6};
-  const int ncaps = b->interleaved ? 1 : 5;  // the position-major fold has no residency cap
+  const int ncaps = b->interleaved ? (b->pairs_ok ? 2 : 1) : 5;
   FoldConfig win = b->fold;
   float fold_ms = 1e30f;
   for (int ui = 0; ui < 3 && err == hipSuccess; ++ui)
     for (int ci = 0; ci < ncaps && err == hipSuccess; ++ci) {
-      const FoldConfig c{unrolls[ui], caps[ci]};
+      const FoldConfig c = b->interleaved ? FoldConfig{unrolls[ui], 0, ci == 0} : FoldConfig{unrolls[ui], caps[ci]};
       const float ms = time_launches([&] { return launch_batch_fold(b, c, s); }, s, e0, e1, 3, &err);
       if (err == hipSuccess && ms < fold_ms) {
         fold_ms = ms;
@@ -1079,7 +1095,7 @@ sfft_status sfft_batch_autotune(sfft_batch_t b, void* stream, sfft_fold_config* 
   b->step_ms = step;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[key] = TuneChoice{tw, double(fold_ms)};
+    g_tune_cache[key] = TuneChoice{tw, double(fold_ms), win.pairs};
   }
   if (best) *best = sfft_fold_config{win.unroll, win.wg_per_cu, double(fold_ms)};
   return SFFT_OK;

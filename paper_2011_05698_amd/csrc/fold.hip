@@ -16,11 +16,14 @@ __global__ __launch_bounds__(kFoldTile) void fold_union_kernel(SigArg arg, const
   fold_union<Ld, KAHAN, U, NU>(load_signal(arg, tl.sig), fold_tile_iter(tl.m), tl.i0);
 }
 
-template <class Ld, bool KAHAN, int U>
+// P = 2: workgroup k takes tiles 2k and 2k + 1, the same items of signal
+// groups g and g + 1 (g even: the tile list puts a block's groups innermost
+// and the host checks that their count is even).
+template <class Ld, bool KAHAN, int U, int P>
 __global__ __launch_bounds__(256) void fold_interleaved_kernel(const SignalDesc* __restrict__ table, uint32_t nsig,
                                                                const FoldTile* __restrict__ tiles) {
-  __shared__ IlvShared<typename Ld::R> sh;
-  fold_tile_ilv<Ld, KAHAN, U>(table, nsig, tiles[blockIdx.x], sh);
+  __shared__ IlvShared<typename Ld::R, P> sh;
+  fold_tile_ilv<Ld, KAHAN, U, P>(table, nsig, tiles[P * blockIdx.x], sh);
 }
 
 int fold_lds_bytes(int wg_per_cu) {
@@ -73,29 +76,37 @@ int launch_fold(int dtype, int kahan, const FoldConfig& cfg, const SigArg& sig, 
   return hipGetLastError();
 }
 
-template <class Ld, bool KAHAN>
+template <class Ld, bool KAHAN, int P>
 static void launch_ilv_u(int unroll, dim3 grid, hipStream_t s, const SignalDesc* table, uint32_t nsig,
                          const FoldTile* d_tiles) {
   const dim3 block(256);
-  if (unroll >= 24) hipLaunchKernelGGL((fold_interleaved_kernel<Ld, KAHAN, 24>), grid, block, 0, s, table, nsig, d_tiles);
-  else if (unroll >= 16) hipLaunchKernelGGL((fold_interleaved_kernel<Ld, KAHAN, 16>), grid, block, 0, s, table, nsig, d_tiles);
-  else hipLaunchKernelGGL((fold_interleaved_kernel<Ld, KAHAN, 8>), grid, block, 0, s, table, nsig, d_tiles);
+  if (unroll >= 24) hipLaunchKernelGGL((fold_interleaved_kernel<Ld, KAHAN, 24, P>), grid, block, 0, s, table, nsig, d_tiles);
+  else if (unroll >= 16) hipLaunchKernelGGL((fold_interleaved_kernel<Ld, KAHAN, 16, P>), grid, block, 0, s, table, nsig, d_tiles);
+  else hipLaunchKernelGGL((fold_interleaved_kernel<Ld, KAHAN, 8, P>), grid, block, 0, s, table, nsig, d_tiles);
 }
 
-int launch_fold_interleaved(int dtype, int kahan, int unroll, const SignalDesc* table, uint32_t nsig,
+template <class Ld, bool KAHAN>
+static void launch_ilv_p(bool pairs, uint32_t ntiles, hipStream_t s, int unroll, const SignalDesc* table,
+                         uint32_t nsig, const FoldTile* d_tiles) {
+  if (pairs) launch_ilv_u<Ld, KAHAN, 2>(unroll, dim3(ntiles / 2), s, table, nsig, d_tiles);
+  else launch_ilv_u<Ld, KAHAN, 1>(unroll, dim3(ntiles), s, table, nsig, d_tiles);
+}
+
+int launch_fold_interleaved(int dtype, int kahan, int unroll, bool pairs, const SignalDesc* table, uint32_t nsig,
                             const FoldTile* d_tiles, uint32_t ntiles, void* stream) {
   if (ntiles == 0 || nsig == 0) return hipSuccess;
+  const uint32_t ngroups = (nsig + uint32_t(kIlvSigs) - 1) / uint32_t(kIlvSigs);
+  if (pairs && (dtype == SFFT_C128 || ngroups % 2 != 0 || nsig % 2 != 0)) return hipErrorInvalidValue;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const dim3 grid(ntiles);
   if (dtype == SFFT_C128) {
-    if (kahan) launch_ilv_u<LoadC128, true>(unroll, grid, s, table, nsig, d_tiles);
-    else launch_ilv_u<LoadC128, false>(unroll, grid, s, table, nsig, d_tiles);
+    if (kahan) launch_ilv_u<LoadC128, true, 1>(unroll, dim3(ntiles), s, table, nsig, d_tiles);
+    else launch_ilv_u<LoadC128, false, 1>(unroll, dim3(ntiles), s, table, nsig, d_tiles);
   } else if (dtype == SFFT_F16X2_SCALED) {
-    if (kahan) launch_ilv_u<LoadF16, true>(unroll, grid, s, table, nsig, d_tiles);
-    else launch_ilv_u<LoadF16, false>(unroll, grid, s, table, nsig, d_tiles);
+    if (kahan) launch_ilv_p<LoadF16, true>(pairs, ntiles, s, unroll, table, nsig, d_tiles);
+    else launch_ilv_p<LoadF16, false>(pairs, ntiles, s, unroll, table, nsig, d_tiles);
   } else {
-    if (kahan) launch_ilv_u<LoadC64, true>(unroll, grid, s, table, nsig, d_tiles);
-    else launch_ilv_u<LoadC64, false>(unroll, grid, s, table, nsig, d_tiles);
+    if (kahan) launch_ilv_p<LoadC64, true>(pairs, ntiles, s, unroll, table, nsig, d_tiles);
+    else launch_ilv_p<LoadC64, false>(pairs, ntiles, s, unroll, table, nsig, d_tiles);
   }
   return hipGetLastError();
 }

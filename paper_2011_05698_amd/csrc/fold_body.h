@@ -28,6 +28,13 @@ struct LoadC64 {
   static __device__ __forceinline__ cplx<float> load(const void* x, uint64_t i) {
     return reinterpret_cast<const cplx<float>*>(x)[i];
   }
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  // elements i and i + 1 in one 16-byte load (x + i 16-byte aligned)
+  static __device__ __forceinline__ void load2(const void* x, uint64_t i, cplx<float>* v) {
+    const f4 q = *reinterpret_cast<const f4*>(reinterpret_cast<const cplx<float>*>(x) + i);
+    v[0] = {q.x, q.y};
+    v[1] = {q.z, q.w};
+  }
 };
 struct LoadC128 {
   using R = double;
@@ -40,9 +47,16 @@ struct LoadF16 {
   using R = float;
   static constexpr bool kScaled = true;
   typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+  typedef _Float16 h4 __attribute__((ext_vector_type(4)));
   static __device__ __forceinline__ cplx<float> load(const void* x, uint64_t i) {
     const h2 v = reinterpret_cast<const h2*>(x)[i];
     return {float(v.x), float(v.y)};
+  }
+  // elements i and i + 1 in one 8-byte load (x + i 8-byte aligned)
+  static __device__ __forceinline__ void load2(const void* x, uint64_t i, cplx<float>* v) {
+    const h4 q = *reinterpret_cast<const h4*>(reinterpret_cast<const h2*>(x) + i);
+    v[0] = {float(q.x), float(q.y)};
+    v[1] = {float(q.z), float(q.w)};
   }
 };
 
@@ -188,42 +202,52 @@ __device__ __forceinline__ void fold_tile_any(const SignalDesc& sd, const FoldTi
 }
 
 // Position-major batch: the signals share one plan and sample c of signal s
-// sits at x_s + c * ld with x_s = x_0 + s, so for a given tap the 64 signals
-// of a workgroup are 64 adjacent elements of one row.  Lanes are signals and
-// each wave walks the taps of kIlvItems / 4 items: index, tap weight and
-// loop bounds are wave-uniform (scalar), every gather is one contiguous
-// row segment, and the sum for each (item, signal) takes the taps in the same
-// order and arithmetic as fold_kernel.  The kIlvItems x 64 results are
-// transposed through LDS so that each signal's consecutive items are written
-// as one contiguous run.
-// LDS of one position-major fold tile: the kIlvItems x 64 results, and the
-// destination of each signal's run.
-template <typename R>
+// sits at x_s + c * ld with x_s = x_0 + s, so for a given tap the signals of
+// a workgroup are adjacent elements of one row.  Lanes are signals (P = 1)
+// or adjacent pairs of signals (P = 2: one 16-byte load of two complex64
+// samples, or 8 bytes of two FP16 pairs, so that a load instruction moves
+// twice the bytes), and each wave walks the taps of kIlvItems / 4 items:
+// index, tap weight and loop bounds are wave-uniform (scalar), every gather
+// is one contiguous row segment, and the sum for each (item, signal) takes
+// the taps in the same order and arithmetic as fold_kernel, whatever P.
+// The kIlvItems x 64 P results are transposed through LDS so that each
+// signal's consecutive items are written as one contiguous run.
+// LDS of one position-major fold tile: the results, and the destination of
+// each signal's run.
+template <typename R, int P = 1>
 struct IlvShared {
-  cplx<R> tile[kIlvItems][kIlvSigs + 1];
-  cplx<R>* ys[kIlvSigs];
+  cplx<R> tile[kIlvItems][kIlvSigs * P + 1];
+  cplx<R>* ys[kIlvSigs * P];
 };
 
-// One position-major fold tile (kIlvItems items x the 64 signals of group
-// tl.sig) by a workgroup of 256 threads.
-template <class Ld, bool KAHAN, int U>
+// One position-major fold tile (kIlvItems items x the 64 P signals from
+// group tl.sig on, groups of kIlvSigs) by a workgroup of 256 threads.  P = 2
+// takes x_0 aligned to two elements, an even ld and an even signal count,
+// so that each pair is two live signals or none (host-checked).
+template <class Ld, bool KAHAN, int U, int P = 1>
 __device__ __forceinline__ void fold_tile_ilv(const SignalDesc* __restrict__ table, uint32_t nsig, const FoldTile& tl,
-                                              IlvShared<typename Ld::R>& sh) {
+                                              IlvShared<typename Ld::R, P>& sh) {
   using R = typename Ld::R;
+  static_assert(P == 1 || P == 2, "one or two signals per lane");
   constexpr int kPerWave = kIlvItems / 4;
+  constexpr uint32_t kSigs = kIlvSigs * P;
   auto& tile = sh.tile;
   auto& ys = sh.ys;
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const uint32_t s0 = tl.sig * kIlvSigs, s = s0 + lane;
+  const uint32_t s0 = tl.sig * kIlvSigs, s = s0 + lane * P;
   const bool live = s < nsig;
   const SignalDesc& head = table[s0];
   const PlanDesc* pd = head.plan;
   const IterDesc* it = pd->iters + tl.m;
   const uint64_t ld = head.ld;
   const char* xs = live ? reinterpret_cast<const char*>(table[s].x) : nullptr;
-  const R scale = live ? R(table[s].scale) : R(0);
-  if (wave == 0) ys[lane] = live ? reinterpret_cast<cplx<R>*>(table[s].y) + it->y_off : nullptr;
+  R scale[P];
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    scale[p] = live ? R(table[s + p].scale) : R(0);
+    if (wave == 0) ys[lane * P + p] = live ? reinterpret_cast<cplx<R>*>(table[s + p].y) + it->y_off : nullptr;
+  }
   const uint32_t B = it->B, logB = it->logB;
   const uint32_t nmask = pd->N - 1;
   const int32_t h = int32_t(it->h);
@@ -237,34 +261,41 @@ __device__ __forceinline__ void fold_tile_ilv(const SignalDesc* __restrict__ tab
     const int32_t tf = -h + int32_t((b + uint32_t(h)) & (B - 1));
     const uint32_t ntaps = uint32_t(h - tf) / B + 1;
     uint32_t idx = (sigma * (uint32_t(tf) - T)) & nmask;
-    Acc<R, KAHAN> acc;
+    Acc<R, KAHAN> acc[P];
     int32_t t = tf;
     for (uint32_t k0 = 0; k0 < ntaps; k0 += U) {
-      cplx<R> v[U];
+      cplx<R> v[U][P];
       R g[U];
 #pragma unroll
       for (int r = 0; r < U; ++r) {
-        if (k0 + r < ntaps) {
-          v[r] = live ? Ld::load(xs, uint64_t(idx) * ld) : cplx<R>{0, 0};
-          g[r] = G[t < 0 ? -t : t];
+        if (k0 + r < ntaps && live) {
+          if constexpr (P == 2) Ld::load2(xs, uint64_t(idx) * ld, v[r]);
+          else v[r][0] = Ld::load(xs, uint64_t(idx) * ld);
         } else {
-          v[r] = cplx<R>{0, 0};
-          g[r] = R(0);
+#pragma unroll
+          for (int p = 0; p < P; ++p) v[r][p] = cplx<R>{0, 0};
         }
+        g[r] = k0 + r < ntaps ? G[t < 0 ? -t : t] : R(0);
         idx = (idx + step) & nmask;
         t += int32_t(B);
       }
 #pragma unroll
       for (int r = 0; r < U; ++r)
-        if (!KAHAN || k0 + r < ntaps) acc.add(g[r], v[r]);
+        if (!KAHAN || k0 + r < ntaps) {
+#pragma unroll
+          for (int p = 0; p < P; ++p) acc[p].add(g[r], v[r][p]);
+        }
     }
-    cplx<R> out{acc.re, acc.im};
-    if (Ld::kScaled) out = cscale(out, scale);
-    tile[wave * kPerWave + q][lane] = out;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      cplx<R> out{acc[p].re, acc[p].im};
+      if (Ld::kScaled) out = cscale(out, scale[p]);
+      tile[wave * kPerWave + q][lane * P + p] = out;
+    }
   }
   __syncthreads();
   // each group of kIlvItems lanes writes one signal's run of items
-  for (uint32_t e = threadIdx.x; e < uint32_t(kIlvItems * kIlvSigs); e += 256) {
+  for (uint32_t e = threadIdx.x; e < uint32_t(kIlvItems) * kSigs; e += 256) {
     const uint32_t sl = e / kIlvItems, il = e % kIlvItems;
     if (s0 + sl < nsig) ys[sl][tl.i0 + il] = tile[il][sl];
   }

@@ -202,8 +202,9 @@ constexpr int kFoldTile = 256;      // (round, bucket) items per fold work item 
 // signals are gathered at once, so a signal's lines stay in the last-level
 // cache between the rounds and iterations that touch them again.
 struct FoldConfig {
-  int unroll;       // 8, 16 or 24
-  int wg_per_cu;    // 0: no cap; else 2..8
+  int unroll;        // 8, 16 or 24
+  int wg_per_cu;     // 0: no cap; else 2..8
+  bool pairs = true; // position-major: two signals per lane where the bound input allows it
 };
 int fold_lds_bytes(int wg_per_cu);
 constexpr int kIlvItems = 16;      // (round, bucket) items per position-major fold workgroup
@@ -218,8 +219,11 @@ int launch_fold(int dtype, int kahan, const FoldConfig& cfg, const SigArg& sig, 
                 uint32_t ntiles, const FoldSplit& split, void* stream);
 // Position-major batch (one plan; sample c of signal s at table[s].x + c * ld,
 // with table[s].x = table[0].x + s): tiles of kIlvItems items x kIlvSigs
-// signals, FoldTile.sig = index of the signal group.
-int launch_fold_interleaved(int dtype, int kahan, int unroll, const SignalDesc* table, uint32_t nsig,
+// signals, FoldTile.sig = index of the signal group, a block's groups
+// innermost.  pairs: two adjacent signals per lane, one workgroup per two
+// tiles (complex64 or FP16 pairs; the caller checks that x_0 is aligned to
+// two elements and that ld, nsig and the group count are even).
+int launch_fold_interleaved(int dtype, int kahan, int unroll, bool pairs, const SignalDesc* table, uint32_t nsig,
                             const FoldTile* d_tiles, uint32_t ntiles, void* stream);
 int launch_bucket_fft(int dtype, const SigArg& sig, const RoundItem* d_items, const FftGroup* d_groups,
                       const FftGroups& fg, void* stream);

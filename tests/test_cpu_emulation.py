@@ -63,8 +63,8 @@ HOST_CLANG = "/opt/rocm/llvm/bin/clang++"
 
 def _build(main, flavour):
     """Builds an emulation program once per source state (host compiler, no HIP)."""
-    srcs = [os.path.join(EMU, f) for f in ("recover_emu.cpp", "emu_selftest.cpp", "fold_emu.cpp", "hip_emu.h",
-                                           "guarded.h")]
+    srcs = [os.path.join(EMU, f) for f in ("recover_emu.cpp", "emu_selftest.cpp", "fold_emu.cpp", "ilv_emu.cpp",
+                                           "hip_emu.h", "guarded.h")]
     srcs += [os.path.join(EMU, "include", "hip", "hip_runtime.h"), os.path.join(CSRC, "plan.cpp"),
              os.path.join(ROOT, "include", "sfft.h")]
     srcs += [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC)) if f.endswith(".h")]
@@ -75,12 +75,12 @@ def _build(main, flavour):
     exe = os.path.join(BUILD, f"{main}_{flavour}_{h.hexdigest()[:16]}")
     if os.path.exists(exe):
         return exe
-    gxx = HOST_CLANG if main == "fold_emu" else shutil.which("g++")
+    gxx = HOST_CLANG if main in ("fold_emu", "ilv_emu") else shutil.which("g++")
     if not gxx or not os.path.exists(gxx):
         pytest.skip(f"host compiler for {main} not found")
     os.makedirs(BUILD, exist_ok=True)
     tmp = f"{exe}.{os.getpid()}.tmp"  # parallel test workers may build the same program
-    extra = [os.path.join(CSRC, "plan.cpp")] if main in ("recover_emu", "fold_emu") else []
+    extra = [os.path.join(CSRC, "plan.cpp")] if main in ("recover_emu", "fold_emu", "ilv_emu") else []
     subprocess.run([gxx, "-std=c++17", *flags, "-g", "-pthread", "-Wno-unknown-pragmas",
                     "-I", os.path.join(EMU, "include"), "-I", EMU, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
                     os.path.join(EMU, main + ".cpp"), *extra, "-o", tmp], check=True, capture_output=True)
@@ -194,6 +194,33 @@ def test_emulated_fold_union_tiles_bit_exact(case, flavour):
             assert r.stdout.startswith("FOLD OK") and " union 0 " not in r.stdout, r.stdout
             if counts:
                 assert f"tiles {counts[0]} union {counts[1]} " in r.stdout, r.stdout
+
+
+ILV_CASES = [
+    # dtype, Kahan, signals, ld, guard mode, two signals per lane
+    (0, 0, 100, 102, 0, 1),   # complex64, two ragged groups of 64 -> one pair workgroup per block
+    (2, 1, 100, 102, 1, 1),   # FP16 pairs with per-signal scales, Kahan
+    (2, 0, 100, 101, 0, 0),   # odd ld: one signal per lane
+    (0, 0, 65, 66, 1, 0),     # odd signal count
+    (1, 1, 5, 5, 0, 0),       # complex128: always one signal per lane
+]
+
+
+@pytest.mark.parametrize("case", ILV_CASES, ids=lambda c: f"d{c[0]}_k{c[1]}_n{c[2]}_ld{c[3]}_g{c[4]}")
+def test_emulated_position_major_fold_bit_exact(case):
+    """The position-major fold body, with one and with two adjacent signals
+    per lane, gives every signal's bucket values bit for bit what the
+    per-signal fold gives on a contiguous copy of that signal, for 8, 16
+    and 24 taps in flight; every item is written and every access stays
+    inside its buffer (guard pages after or before every buffer).  Two
+    signals per lane run exactly where the library takes them (complex64 or
+    FP16 storage, even ld, even signal and group counts)."""
+    exe = _build("ilv_emu", "plain")
+    dtype, kahan, nsig, ld, mode, pairs = case
+    args = [str(a) for a in (2 ** 12, 10, 128, 1793, 4, 16, 1, 1e-6, 900, dtype, kahan, mode, nsig, ld)]
+    r = subprocess.run([exe, *args], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, (args, r.returncode, r.stdout[-2000:], r.stderr[-2000:])
+    assert r.stdout.startswith("ILV OK") and r.stdout.rstrip().endswith(f"pairs {pairs}"), r.stdout
 
 
 def test_emulated_recovery_sanitized(tmp_path):
