@@ -138,7 +138,7 @@ struct sfft_batch_s {
   FoldConfig fold{8, 0};
   bool interleaved = false;         // one plan, position-major signals (sfft_batch_create_interleaved)
   uint32_t ngroups = 0;             // interleaved: signal groups of kIlvSigs
-  bool pairs_ok = false;            // interleaved: the bound input can take two signals per fold lane
+  int lanes_max = 1;                // interleaved: most signals per fold lane the bound input allows
   // bucket-DFT grouping: round items (host copy) cut into groups of at most fft_group_points points
   std::vector<RoundItem> h_items;
   uint32_t fft_group_points = kFftGroupPoints;
@@ -446,7 +446,8 @@ sfft_status regroup_fft(sfft_batch_s* b, uint32_t points) {
 
 int launch_batch_fold(const sfft_batch_s* b, const FoldConfig& cfg, hipStream_t s) {
   if (b->interleaved)
-    return launch_fold_interleaved(b->dtype, b->kahan, cfg.unroll, b->pairs_ok && cfg.pairs, b->d_sigs,
+    return launch_fold_interleaved(b->dtype, b->kahan, cfg.unroll,
+                                   cfg.lanes == 0 ? b->lanes_max : std::min(cfg.lanes, b->lanes_max), b->d_sigs,
                                    uint32_t(b->plans.size()), b->d_tiles, b->ntiles, s);
   return launch_fold(b->dtype, b->kahan, cfg, table_arg(b), b->d_tiles, b->ntiles, b->split, s);
 }
@@ -846,15 +847,22 @@ sfft_status sfft_execute_interleaved(sfft_batch_t b, const void* d_x, int64_t ld
     sd.scale = h_scale ? h_scale[i] : 1.0f;
     sd.ld = uint32_t(ld);
   }
-  // two signals per fold lane where each lane's pair is one aligned load of
-  // two live signals (and the fold shape takes them); a change either way
-  // captures the graph again
-  const bool pairs_ok = b->dtype != SFFT_C128 && b->ngroups % 2 == 0 && n % 2 == 0 && ld % 2 == 0 &&
-                        reinterpret_cast<uintptr_t>(d_x) % (2 * es) == 0;
-  if (pairs_ok != b->pairs_ok) {
+  // L adjacent signals per fold lane where each lane's run is one aligned
+  // load of L live signals: L = 2 for complex64, 2 or 4 for FP16 pairs (the
+  // fold shape picks up to this many); a change captures the graph again
+  int lanes_max = 1;
+  for (int L : {4, 2}) {
+    const int most = b->dtype == SFFT_C128 ? 1 : b->dtype == SFFT_F16X2_SCALED ? 4 : 2;
+    if (L <= most && b->ngroups % uint32_t(L) == 0 && n % size_t(L) == 0 && ld % L == 0 &&
+        reinterpret_cast<uintptr_t>(d_x) % (uint64_t(L) * es) == 0) {
+      lanes_max = L;
+      break;
+    }
+  }
+  if (lanes_max != b->lanes_max) {
     const sfft_status st = drop_graph(b);
     if (st != SFFT_OK) return st;
-    b->pairs_ok = pairs_ok;
+    b->lanes_max = lanes_max;
   }
   return bind_and_replay(b, sig, reinterpret_cast<hipStream_t>(stream));
 }
@@ -900,7 +908,7 @@ sfft_status sfft_plan_set_fold_config(sfft_plan_t p, const sfft_fold_config* cfg
 
 sfft_status sfft_batch_set_fold_config(sfft_batch_t b, const sfft_fold_config* cfg) {
   if (!b || !valid_fold(cfg)) return fail(SFFT_ERR_PARAM, "invalid fold configuration");
-  b->fold = FoldConfig{cfg->unroll, cfg->wg_per_cu, b->fold.pairs};
+  b->fold = FoldConfig{cfg->unroll, cfg->wg_per_cu, b->fold.lanes};
   return drop_graph(b);
 }
 
@@ -942,7 +950,7 @@ sfft_status sfft_batch_set_tuning(sfft_batch_t b, const sfft_batch_tuning* t) {
     b->fused_chunk = uint32_t(t->fused_chunk);
   }
   b->mode = t->mode;
-  b->fold = FoldConfig{t->fold_unroll, t->fold_wg_per_cu, b->fold.pairs};
+  b->fold = FoldConfig{t->fold_unroll, t->fold_wg_per_cu, b->fold.lanes};
   return SFFT_OK;
 }
 
@@ -955,13 +963,14 @@ std::mutex g_tune_mu;
 struct TuneChoice {
   sfft_batch_tuning tuning;
   double fold_ms;  // the winning fold shape's mean time when it was chosen
-  bool fold_pairs; // position-major: two signals per fold lane
+  int fold_lanes;  // position-major: signals per fold lane
 };
 std::map<std::string, TuneChoice> g_tune_cache;
 
 std::string tuning_key(const sfft_batch_s* b) {
-  std::string k = std::to_string(b->dtype) + "/" + std::to_string(b->kahan) + "/" + (b->interleaved ? (b->pairs_ok ? "pm2" : "pm") : "ps") +
-                  "/" + std::to_string(b->plans.size());
+  const std::string layout = b->interleaved ? "pm" + std::to_string(b->lanes_max) : std::string("ps");
+  std::string k = std::to_string(b->dtype) + "/" + std::to_string(b->kahan) + "/" + layout + "/" +
+                  std::to_string(b->plans.size());
   uint64_t h = 1469598103934665603ull;  // FNV-1a over every plan's shape
   for (const sfft_plan_t p : b->plans) {
     const uint64_t v[6] = {uint64_t(p->hp.N), uint64_t(p->hp.B), uint64_t(p->hp.w), uint64_t(p->hp.loops),
@@ -1002,7 +1011,7 @@ sfft_status sfft_batch_autotune(sfft_batch_t b, void* stream, sfft_fold_config* 
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto hit = g_tune_cache.find(key);
     if (hit != g_tune_cache.end()) {
-      b->fold.pairs = hit->second.fold_pairs;
+      b->fold.lanes = hit->second.fold_lanes;
       sfft_status st = sfft_batch_set_tuning(b, &hit->second.tuning);
       if (st != SFFT_OK) return st;
       b->step_ms = float(hit->second.tuning.step_ms);
@@ -1018,15 +1027,16 @@ sfft_status sfft_batch_autotune(sfft_batch_t b, void* stream, sfft_fold_config* 
   int err = hipSuccess;
   const SigArg a = table_arg(b);
   // 1. fold launch shape: taps in flight x residency cap (per-signal layout)
-  //    or x signals per lane (position-major, where the input allows two)
+  //    or x signals per lane (position-major: 1, 2 or 4, as the input allows)
   const int unrolls[3] = {8, 16, 24};
   const int caps[5] = {0, 2, 3, 4, 6};
-  const int ncaps = b->interleaved ? (b->pairs_ok ? 2 : 1) : 5;
+  const int lanes[3] = {1, 2, 4};
+  const int ncaps = b->interleaved ? (b->lanes_max == 4 ? 3 : b->lanes_max) : 5;
   FoldConfig win = b->fold;
   float fold_ms = 1e30f;
   for (int ui = 0; ui < 3 && err == hipSuccess; ++ui)
     for (int ci = 0; ci < ncaps && err == hipSuccess; ++ci) {
-      const FoldConfig c = b->interleaved ? FoldConfig{unrolls[ui], 0, ci == 0} : FoldConfig{unrolls[ui], caps[ci]};
+      const FoldConfig c = b->interleaved ? FoldConfig{unrolls[ui], 0, lanes[ci]} : FoldConfig{unrolls[ui], caps[ci]};
       const float ms = time_launches([&] { return launch_batch_fold(b, c, s); }, s, e0, e1, 3, &err);
       if (err == hipSuccess && ms < fold_ms) {
         fold_ms = ms;
@@ -1095,7 +1105,7 @@ sfft_status sfft_batch_autotune(sfft_batch_t b, void* stream, sfft_fold_config* 
   b->step_ms = step;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[key] = TuneChoice{tw, double(fold_ms), win.pairs};
+    g_tune_cache[key] = TuneChoice{tw, double(fold_ms), win.lanes};
   }
   if (best) *best = sfft_fold_config{win.unroll, win.wg_per_cu, double(fold_ms)};
   return SFFT_OK;

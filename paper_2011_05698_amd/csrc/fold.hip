@@ -1,5 +1,7 @@
 // Stage kernels of the fold: one workgroup per tile (device bodies in
 // fold_body.h); union tiles and one-round tiles in kernels of their own.
+#include <type_traits>
+
 #include "fold_body.h"
 
 namespace sfft {
@@ -16,9 +18,9 @@ __global__ __launch_bounds__(kFoldTile) void fold_union_kernel(SigArg arg, const
   fold_union<Ld, KAHAN, U, NU>(load_signal(arg, tl.sig), fold_tile_iter(tl.m), tl.i0);
 }
 
-// P = 2: workgroup k takes tiles 2k and 2k + 1, the same items of signal
-// groups g and g + 1 (g even: the tile list puts a block's groups innermost
-// and the host checks that their count is even).
+// P > 1: workgroup k takes tiles P k .. P k + P - 1, the same items of signal
+// groups g .. g + P - 1 (g a multiple of P: the tile list puts a block's
+// groups innermost and the host checks that their count is a multiple of P).
 template <class Ld, bool KAHAN, int U, int P>
 __global__ __launch_bounds__(256) void fold_interleaved_kernel(const SignalDesc* __restrict__ table, uint32_t nsig,
                                                                const FoldTile* __restrict__ tiles) {
@@ -86,27 +88,33 @@ static void launch_ilv_u(int unroll, dim3 grid, hipStream_t s, const SignalDesc*
 }
 
 template <class Ld, bool KAHAN>
-static void launch_ilv_p(bool pairs, uint32_t ntiles, hipStream_t s, int unroll, const SignalDesc* table,
+static void launch_ilv_p(int lanes, uint32_t ntiles, hipStream_t s, int unroll, const SignalDesc* table,
                          uint32_t nsig, const FoldTile* d_tiles) {
-  if (pairs) launch_ilv_u<Ld, KAHAN, 2>(unroll, dim3(ntiles / 2), s, table, nsig, d_tiles);
+  if constexpr (std::is_same<Ld, LoadF16>::value) {
+    if (lanes == 4) return launch_ilv_u<Ld, KAHAN, 4>(unroll, dim3(ntiles / 4), s, table, nsig, d_tiles);
+  }
+  if (lanes == 2) launch_ilv_u<Ld, KAHAN, 2>(unroll, dim3(ntiles / 2), s, table, nsig, d_tiles);
   else launch_ilv_u<Ld, KAHAN, 1>(unroll, dim3(ntiles), s, table, nsig, d_tiles);
 }
 
-int launch_fold_interleaved(int dtype, int kahan, int unroll, bool pairs, const SignalDesc* table, uint32_t nsig,
+int launch_fold_interleaved(int dtype, int kahan, int unroll, int lanes, const SignalDesc* table, uint32_t nsig,
                             const FoldTile* d_tiles, uint32_t ntiles, void* stream) {
   if (ntiles == 0 || nsig == 0) return hipSuccess;
   const uint32_t ngroups = (nsig + uint32_t(kIlvSigs) - 1) / uint32_t(kIlvSigs);
-  if (pairs && (dtype == SFFT_C128 || ngroups % 2 != 0 || nsig % 2 != 0)) return hipErrorInvalidValue;
+  const int most = dtype == SFFT_C128 ? 1 : dtype == SFFT_F16X2_SCALED ? 4 : 2;
+  if ((lanes != 1 && lanes != 2 && lanes != 4) || lanes > most || ngroups % uint32_t(lanes) != 0 ||
+      nsig % uint32_t(lanes) != 0)
+    return hipErrorInvalidValue;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (dtype == SFFT_C128) {
     if (kahan) launch_ilv_u<LoadC128, true, 1>(unroll, dim3(ntiles), s, table, nsig, d_tiles);
     else launch_ilv_u<LoadC128, false, 1>(unroll, dim3(ntiles), s, table, nsig, d_tiles);
   } else if (dtype == SFFT_F16X2_SCALED) {
-    if (kahan) launch_ilv_p<LoadF16, true>(pairs, ntiles, s, unroll, table, nsig, d_tiles);
-    else launch_ilv_p<LoadF16, false>(pairs, ntiles, s, unroll, table, nsig, d_tiles);
+    if (kahan) launch_ilv_p<LoadF16, true>(lanes, ntiles, s, unroll, table, nsig, d_tiles);
+    else launch_ilv_p<LoadF16, false>(lanes, ntiles, s, unroll, table, nsig, d_tiles);
   } else {
-    if (kahan) launch_ilv_p<LoadC64, true>(pairs, ntiles, s, unroll, table, nsig, d_tiles);
-    else launch_ilv_p<LoadC64, false>(pairs, ntiles, s, unroll, table, nsig, d_tiles);
+    if (kahan) launch_ilv_p<LoadC64, true>(lanes, ntiles, s, unroll, table, nsig, d_tiles);
+    else launch_ilv_p<LoadC64, false>(lanes, ntiles, s, unroll, table, nsig, d_tiles);
   }
   return hipGetLastError();
 }

@@ -52,11 +52,20 @@ struct LoadF16 {
     const h2 v = reinterpret_cast<const h2*>(x)[i];
     return {float(v.x), float(v.y)};
   }
+  typedef _Float16 h8 __attribute__((ext_vector_type(8)));
   // elements i and i + 1 in one 8-byte load (x + i 8-byte aligned)
   static __device__ __forceinline__ void load2(const void* x, uint64_t i, cplx<float>* v) {
     const h4 q = *reinterpret_cast<const h4*>(reinterpret_cast<const h2*>(x) + i);
     v[0] = {float(q.x), float(q.y)};
     v[1] = {float(q.z), float(q.w)};
+  }
+  // elements i .. i + 3 in one 16-byte load (x + i 16-byte aligned)
+  static __device__ __forceinline__ void load4(const void* x, uint64_t i, cplx<float>* v) {
+    const h8 q = *reinterpret_cast<const h8*>(reinterpret_cast<const h2*>(x) + i);
+    v[0] = {float(q[0]), float(q[1])};
+    v[1] = {float(q[2]), float(q[3])};
+    v[2] = {float(q[4]), float(q[5])};
+    v[3] = {float(q[6]), float(q[7])};
   }
 };
 
@@ -204,9 +213,10 @@ __device__ __forceinline__ void fold_tile_any(const SignalDesc& sd, const FoldTi
 // Position-major batch: the signals share one plan and sample c of signal s
 // sits at x_s + c * ld with x_s = x_0 + s, so for a given tap the signals of
 // a workgroup are adjacent elements of one row.  Lanes are signals (P = 1)
-// or adjacent pairs of signals (P = 2: one 16-byte load of two complex64
-// samples, or 8 bytes of two FP16 pairs, so that a load instruction moves
-// twice the bytes), and each wave walks the taps of kIlvItems / 4 items:
+// or runs of P adjacent signals (P = 2: one 16-byte load of two complex64
+// samples, or 8 bytes of two FP16 pairs; P = 4, FP16 pairs only: one
+// 16-byte load of four), so that a load instruction moves P times the
+// bytes, and each wave walks the taps of kIlvItems / 4 items:
 // index, tap weight and loop bounds are wave-uniform (scalar), every gather
 // is one contiguous row segment, and the sum for each (item, signal) takes
 // the taps in the same order and arithmetic as fold_kernel, whatever P.
@@ -221,14 +231,14 @@ struct IlvShared {
 };
 
 // One position-major fold tile (kIlvItems items x the 64 P signals from
-// group tl.sig on, groups of kIlvSigs) by a workgroup of 256 threads.  P = 2
-// takes x_0 aligned to two elements, an even ld and an even signal count,
-// so that each pair is two live signals or none (host-checked).
+// group tl.sig on, groups of kIlvSigs) by a workgroup of 256 threads.  P > 1
+// takes x_0 aligned to P elements and ld and the signal count multiples of
+// P, so that each lane's run is P live signals or none (host-checked).
 template <class Ld, bool KAHAN, int U, int P = 1>
 __device__ __forceinline__ void fold_tile_ilv(const SignalDesc* __restrict__ table, uint32_t nsig, const FoldTile& tl,
                                               IlvShared<typename Ld::R, P>& sh) {
   using R = typename Ld::R;
-  static_assert(P == 1 || P == 2, "one or two signals per lane");
+  static_assert(P == 1 || P == 2 || P == 4, "one, two or four signals per lane");
   constexpr int kPerWave = kIlvItems / 4;
   constexpr uint32_t kSigs = kIlvSigs * P;
   auto& tile = sh.tile;
@@ -269,7 +279,8 @@ __device__ __forceinline__ void fold_tile_ilv(const SignalDesc* __restrict__ tab
 #pragma unroll
       for (int r = 0; r < U; ++r) {
         if (k0 + r < ntaps && live) {
-          if constexpr (P == 2) Ld::load2(xs, uint64_t(idx) * ld, v[r]);
+          if constexpr (P == 4) Ld::load4(xs, uint64_t(idx) * ld, v[r]);
+          else if constexpr (P == 2) Ld::load2(xs, uint64_t(idx) * ld, v[r]);
           else v[r][0] = Ld::load(xs, uint64_t(idx) * ld);
         } else {
 #pragma unroll

@@ -204,7 +204,7 @@ constexpr int kFoldTile = 256;      // (round, bucket) items per fold work item 
 struct FoldConfig {
   int unroll;        // 8, 16 or 24
   int wg_per_cu;     // 0: no cap; else 2..8
-  bool pairs = true; // position-major: two signals per lane where the bound input allows it
+  int lanes = 0;     // position-major: signals per lane (1, 2 or 4); 0: as many as the bound input allows
 };
 int fold_lds_bytes(int wg_per_cu);
 constexpr int kIlvItems = 16;      // (round, bucket) items per position-major fold workgroup
@@ -220,10 +220,11 @@ int launch_fold(int dtype, int kahan, const FoldConfig& cfg, const SigArg& sig, 
 // Position-major batch (one plan; sample c of signal s at table[s].x + c * ld,
 // with table[s].x = table[0].x + s): tiles of kIlvItems items x kIlvSigs
 // signals, FoldTile.sig = index of the signal group, a block's groups
-// innermost.  pairs: two adjacent signals per lane, one workgroup per two
-// tiles (complex64 or FP16 pairs; the caller checks that x_0 is aligned to
-// two elements and that ld, nsig and the group count are even).
-int launch_fold_interleaved(int dtype, int kahan, int unroll, bool pairs, const SignalDesc* table, uint32_t nsig,
+// innermost.  lanes: adjacent signals per lane (1; 2 for complex64 and FP16
+// pairs; 4 for FP16 pairs), one workgroup per `lanes` tiles; the caller
+// checks that x_0 is aligned to `lanes` elements and that ld is a multiple
+// of it (nsig and the group count are checked here).
+int launch_fold_interleaved(int dtype, int kahan, int unroll, int lanes, const SignalDesc* table, uint32_t nsig,
                             const FoldTile* d_tiles, uint32_t ntiles, void* stream);
 int launch_bucket_fft(int dtype, const SigArg& sig, const RoundItem* d_items, const FftGroup* d_groups,
                       const FftGroups& fg, void* stream);

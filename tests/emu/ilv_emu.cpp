@@ -6,9 +6,10 @@
 //     one-round tiles (fold_tile) with 8 taps in flight;
 //   * the position-major tile list (interleaved_tiles) with one signal per
 //     lane, 8, 16 and 24 taps in flight;
-//   * the same with two adjacent signals per lane (one workgroup per two
-//     tiles), where the library takes that form: complex64 or FP16 storage,
-//     an even ld, an even signal count and an even number of signal groups.
+//   * the same with two, then four, adjacent signals per lane (one
+//     workgroup per two or four tiles), where the library allows that form:
+//     two for complex64, two or four for FP16 pairs, with ld, the signal
+//     count and the number of signal groups multiples of it.
 // Every bucket array must equal the reference bit for bit and every item
 // must be written.  X, the descriptor table, the plan tables, each signal's
 // bucket array and the workgroup's LDS sit against an inaccessible guard
@@ -17,7 +18,7 @@
 //
 // usage: ilv_emu N K B w loops l q delta seed dtype kahan guard_mode nsig ld
 // dtype: 0 complex64, 1 complex128, 2 FP16 pairs with per-signal scales.
-// Prints "ILV OK tiles <n> pairs <0|1>" and exits 0, or names the first
+// Prints "ILV OK tiles <n> lanes <1|2|4>" and exits 0, or names the first
 // mismatch and exits 1.
 #include <cstdio>
 #include <cstdlib>
@@ -132,9 +133,15 @@ int run(const HostPlan& hp, uint64_t seed, uint32_t nsig, uint32_t ld) {
   interleaved_tiles(hp, ngroups, tiles);
   auto* d_tiles = static_cast<FoldTile*>(galloc(sizeof(FoldTile) * tiles.size(), "tile list"));
   std::memcpy(d_tiles, tiles.data(), sizeof(FoldTile) * tiles.size());
-  // the library's test for two signals per lane
-  const bool pairs = !std::is_same<Ld, LoadC128>::value && ngroups % 2 == 0 && nsig % 2 == 0 && ld % 2 == 0 &&
-                     reinterpret_cast<uintptr_t>(X) % (2 * es) == 0;
+  // the library's test for L signals per lane
+  int lanes = 1;
+  const int most = std::is_same<Ld, LoadC128>::value ? 1 : kF16 ? 4 : 2;
+  for (int L : {4, 2})
+    if (L <= most && ngroups % uint32_t(L) == 0 && nsig % uint32_t(L) == 0 && ld % uint32_t(L) == 0 &&
+        reinterpret_cast<uintptr_t>(X) % (uint64_t(L) * es) == 0) {
+      lanes = L;
+      break;
+    }
 
   auto check = [&](const char* what) -> bool {
     cplx<R> ones;
@@ -167,17 +174,25 @@ int run(const HostPlan& hp, uint64_t seed, uint32_t nsig, uint32_t ld) {
   };
   using one = std::integral_constant<int, 1>;
   using two = std::integral_constant<int, 2>;
+  using four = std::integral_constant<int, 4>;
   if (!launch(std::integral_constant<int, 8>{}, one{})) return 1;
   if (!launch(std::integral_constant<int, 16>{}, one{})) return 1;
   if (!launch(std::integral_constant<int, 24>{}, one{})) return 1;
   if constexpr (!std::is_same<Ld, LoadC128>::value) {
-    if (pairs) {
+    if (lanes >= 2) {
       if (!launch(std::integral_constant<int, 8>{}, two{})) return 1;
       if (!launch(std::integral_constant<int, 16>{}, two{})) return 1;
       if (!launch(std::integral_constant<int, 24>{}, two{})) return 1;
     }
   }
-  std::printf("ILV OK tiles %zu pairs %d\n", tiles.size(), int(pairs));
+  if constexpr (kF16) {
+    if (lanes == 4) {
+      if (!launch(std::integral_constant<int, 8>{}, four{})) return 1;
+      if (!launch(std::integral_constant<int, 16>{}, four{})) return 1;
+      if (!launch(std::integral_constant<int, 24>{}, four{})) return 1;
+    }
+  }
+  std::printf("ILV OK tiles %zu lanes %d\n", tiles.size(), lanes);
   return 0;
 }
 

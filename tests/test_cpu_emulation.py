@@ -197,30 +197,32 @@ def test_emulated_fold_union_tiles_bit_exact(case, flavour):
 
 
 ILV_CASES = [
-    # dtype, Kahan, signals, ld, guard mode, two signals per lane
-    (0, 0, 100, 102, 0, 1),   # complex64, two ragged groups of 64 -> one pair workgroup per block
-    (2, 1, 100, 102, 1, 1),   # FP16 pairs with per-signal scales, Kahan
-    (2, 0, 100, 101, 0, 0),   # odd ld: one signal per lane
-    (0, 0, 65, 66, 1, 0),     # odd signal count
-    (1, 1, 5, 5, 0, 0),       # complex128: always one signal per lane
+    # dtype, Kahan, signals, ld, guard mode, most signals per lane
+    (0, 0, 100, 102, 0, 2),   # complex64, two groups of 64 (the last ragged): one workgroup per two tiles
+    (2, 1, 100, 102, 1, 2),   # FP16 pairs with per-signal scales, Kahan; ld not a multiple of 4
+    (2, 0, 200, 204, 0, 4),   # FP16 pairs, four groups (the last ragged): one workgroup per four tiles
+    (2, 0, 100, 101, 1, 1),   # odd ld: one signal per lane
+    (0, 0, 65, 66, 1, 1),     # odd signal count
+    (1, 1, 5, 5, 0, 1),       # complex128: always one signal per lane
 ]
 
 
 @pytest.mark.parametrize("case", ILV_CASES, ids=lambda c: f"d{c[0]}_k{c[1]}_n{c[2]}_ld{c[3]}_g{c[4]}")
 def test_emulated_position_major_fold_bit_exact(case):
-    """The position-major fold body, with one and with two adjacent signals
+    """The position-major fold body, with one, two and four adjacent signals
     per lane, gives every signal's bucket values bit for bit what the
     per-signal fold gives on a contiguous copy of that signal, for 8, 16
     and 24 taps in flight; every item is written and every access stays
-    inside its buffer (guard pages after or before every buffer).  Two
-    signals per lane run exactly where the library takes them (complex64 or
-    FP16 storage, even ld, even signal and group counts)."""
+    inside its buffer (guard pages after or before every buffer).  L > 1
+    signals per lane run exactly where the library allows them (two for
+    complex64, two or four for FP16 pairs; ld, the signal count and the
+    group count multiples of L)."""
     exe = _build("ilv_emu", "plain")
-    dtype, kahan, nsig, ld, mode, pairs = case
+    dtype, kahan, nsig, ld, mode, lanes = case
     args = [str(a) for a in (2 ** 12, 10, 128, 1793, 4, 16, 1, 1e-6, 900, dtype, kahan, mode, nsig, ld)]
     r = subprocess.run([exe, *args], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, (args, r.returncode, r.stdout[-2000:], r.stderr[-2000:])
-    assert r.stdout.startswith("ILV OK") and r.stdout.rstrip().endswith(f"pairs {pairs}"), r.stdout
+    assert r.stdout.startswith("ILV OK") and r.stdout.rstrip().endswith(f"lanes {lanes}"), r.stdout
 
 
 def test_emulated_recovery_sanitized(tmp_path):

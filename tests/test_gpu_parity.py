@@ -533,14 +533,16 @@ def _position_major(xs_dev, ld, dtype):
 
 
 @pytest.mark.parametrize("dtype,kahan,nsig,ld", [("c64", False, 70, 72), ("c128", True, 5, 5), ("f16x2", False, 66, 67),
-                                                  ("f16x2", True, 66, 68)],
-                         ids=["c64_70sig_ragged_pairs", "c128_kahan_5sig", "f16x2_66sig", "f16x2_kahan_66sig_pairs"])
+                                                  ("f16x2", True, 66, 68), ("f16x2", False, 200, 204)],
+                         ids=["c64_70sig_ragged_pairs", "c128_kahan_5sig", "f16x2_66sig", "f16x2_kahan_66sig_pairs",
+                              "f16x2_200sig_quads"])
 def test_position_major_matches_single(sf, dtype, kahan, nsig, ld):
     """A position-major batch (one plan, sample c of signal s at X[c, s]) gives
     bit for bit what single executes of the same plan give, for a ragged
     last signal group and every storage form, with one signal per fold lane
-    (odd ld, one group, complex128) and two (complex64 and FP16 pairs with
-    an even ld and two groups); sampled signals match the oracle."""
+    (odd ld, one group, complex128), two (complex64 and FP16 pairs with an
+    even ld and two groups) and up to four (FP16 pairs, ld and the signal
+    count multiples of 4, four groups); sampled signals match the oracle."""
     _check_position_major(sf, dtype, kahan, nsig, ld)
 
 
