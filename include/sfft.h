@@ -353,6 +353,13 @@ typedef struct {
   int32_t fft_group_points; /* STAGES: bucket-DFT points per workgroup */
   int32_t fused_available;  /* read only: 1 if the batch can run FUSED */
   double step_ms;           /* read only: one step of this configuration, as sfft_batch_autotune timed it */
+  int32_t fold_lanes;       /* STAGES, position-major: adjacent signals per fold lane, 1, 2 (complex64,
+                               FP16 pairs) or 4 (FP16 pairs), or 0 for as many as the bound input allows
+                               (the default).  L > 1 needs the input aligned to L elements and ld, the
+                               signal count and the number of 64-signal groups multiples of L; otherwise
+                               the fold takes the largest allowed count below L.  Read back: the count the
+                               bound input runs with (1 for a per-signal batch; before the first
+                               execute, the setting) */
 } sfft_batch_tuning;
 sfft_status sfft_batch_get_tuning(sfft_batch_t b, sfft_batch_tuning* t);
 sfft_status sfft_batch_set_tuning(sfft_batch_t b, const sfft_batch_tuning* t);

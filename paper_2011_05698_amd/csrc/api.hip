@@ -444,10 +444,15 @@ sfft_status regroup_fft(sfft_batch_s* b, uint32_t points) {
   return SFFT_OK;
 }
 
+// Signals per lane of the position-major fold: the shape's count, or as many
+// as the bound input allows (0), never more than it allows.
+int fold_lanes(const sfft_batch_s* b, const FoldConfig& cfg) {
+  return cfg.lanes == 0 ? b->lanes_max : std::min(cfg.lanes, b->lanes_max);
+}
+
 int launch_batch_fold(const sfft_batch_s* b, const FoldConfig& cfg, hipStream_t s) {
   if (b->interleaved)
-    return launch_fold_interleaved(b->dtype, b->kahan, cfg.unroll,
-                                   cfg.lanes == 0 ? b->lanes_max : std::min(cfg.lanes, b->lanes_max), b->d_sigs,
+    return launch_fold_interleaved(b->dtype, b->kahan, cfg.unroll, fold_lanes(b, cfg), b->d_sigs,
                                    uint32_t(b->plans.size()), b->d_tiles, b->ntiles, s);
   return launch_fold(b->dtype, b->kahan, cfg, table_arg(b), b->d_tiles, b->ntiles, b->split, s);
 }
@@ -922,6 +927,7 @@ sfft_status sfft_batch_get_tuning(sfft_batch_t b, sfft_batch_tuning* t) {
   t->fft_group_points = int32_t(b->fft_group_points);
   t->fused_available = b->fused_ok ? 1 : 0;
   t->step_ms = double(b->step_ms);
+  t->fold_lanes = !b->interleaved ? 1 : b->has_binding ? fold_lanes(b, b->fold) : b->fold.lanes;
   return SFFT_OK;
 }
 
@@ -936,6 +942,8 @@ sfft_status sfft_batch_set_tuning(sfft_batch_t b, const sfft_batch_tuning* t) {
     return fail(SFFT_ERR_PARAM, "fused_chunk must be in 1 .. the number of signals (or groups of 64)");
   if (t->fft_group_points != 1024 && t->fft_group_points != 2048 && t->fft_group_points != 4096)
     return fail(SFFT_ERR_PARAM, "fft_group_points must be 1024, 2048 or 4096");
+  if (t->fold_lanes != 0 && t->fold_lanes != 1 && t->fold_lanes != 2 && t->fold_lanes != 4)
+    return fail(SFFT_ERR_PARAM, "fold_lanes must be 0, 1, 2 or 4");
   sfft_status st = drop_graph(b);  // the device lists below are read by the last replay
   if (st != SFFT_OK) return st;
   if (uint32_t(t->fft_group_points) != b->fft_group_points) {
@@ -950,7 +958,7 @@ sfft_status sfft_batch_set_tuning(sfft_batch_t b, const sfft_batch_tuning* t) {
     b->fused_chunk = uint32_t(t->fused_chunk);
   }
   b->mode = t->mode;
-  b->fold = FoldConfig{t->fold_unroll, t->fold_wg_per_cu, b->fold.lanes};
+  b->fold = FoldConfig{t->fold_unroll, t->fold_wg_per_cu, t->fold_lanes};
   return SFFT_OK;
 }
 
@@ -963,7 +971,6 @@ std::mutex g_tune_mu;
 struct TuneChoice {
   sfft_batch_tuning tuning;
   double fold_ms;  // the winning fold shape's mean time when it was chosen
-  int fold_lanes;  // position-major: signals per fold lane
 };
 std::map<std::string, TuneChoice> g_tune_cache;
 
@@ -1011,7 +1018,6 @@ sfft_status sfft_batch_autotune(sfft_batch_t b, void* stream, sfft_fold_config* 
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto hit = g_tune_cache.find(key);
     if (hit != g_tune_cache.end()) {
-      b->fold.lanes = hit->second.fold_lanes;
       sfft_status st = sfft_batch_set_tuning(b, &hit->second.tuning);
       if (st != SFFT_OK) return st;
       b->step_ms = float(hit->second.tuning.step_ms);
@@ -1066,6 +1072,7 @@ sfft_status sfft_batch_autotune(sfft_batch_t b, void* stream, sfft_fold_config* 
   tw.mode = SFFT_BATCH_STAGES;
   tw.fold_unroll = win.unroll;
   tw.fold_wg_per_cu = win.wg_per_cu;
+  tw.fold_lanes = win.lanes;
   tw.fft_group_points = int32_t(fft_win);
   tw.fused_chunk = int32_t(b->fused_chunk);
   float step = 1e30f;
@@ -1105,7 +1112,7 @@ sfft_status sfft_batch_autotune(sfft_batch_t b, void* stream, sfft_fold_config* 
   b->step_ms = step;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[key] = TuneChoice{tw, double(fold_ms), win.lanes};
+    g_tune_cache[key] = TuneChoice{tw, double(fold_ms)};
   }
   if (best) *best = sfft_fold_config{win.unroll, win.wg_per_cu, double(fold_ms)};
   return SFFT_OK;

@@ -52,7 +52,7 @@ class FoldConfig(ctypes.Structure):
 class BatchTuning(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("fused_chunk", ctypes.c_int32), ("fold_unroll", ctypes.c_int32),
                 ("fold_wg_per_cu", ctypes.c_int32), ("fft_group_points", ctypes.c_int32),
-                ("fused_available", ctypes.c_int32), ("step_ms", ctypes.c_double)]
+                ("fused_available", ctypes.c_int32), ("step_ms", ctypes.c_double), ("fold_lanes", ctypes.c_int32)]
 
 
 BATCH_MODES = {"stages": 0, "fused": 1}
@@ -261,11 +261,11 @@ def sfft_batch_get_tuning(batch) -> dict:
     _check(_lib.sfft_batch_get_tuning(batch, ctypes.byref(t)))
     return {"mode": {v: k for k, v in BATCH_MODES.items()}[t.mode], "fused_chunk": t.fused_chunk,
             "fold_unroll": t.fold_unroll, "fold_wg_per_cu": t.fold_wg_per_cu, "fft_group_points": t.fft_group_points,
-            "fused_available": bool(t.fused_available), "step_ms": t.step_ms}
+            "fused_available": bool(t.fused_available), "step_ms": t.step_ms, "fold_lanes": t.fold_lanes}
 
 
-def sfft_batch_set_tuning(batch, mode, fused_chunk, fold_unroll, fold_wg_per_cu, fft_group_points):
-    t = BatchTuning(BATCH_MODES[mode], fused_chunk, fold_unroll, fold_wg_per_cu, fft_group_points, 0, 0.0)
+def sfft_batch_set_tuning(batch, mode, fused_chunk, fold_unroll, fold_wg_per_cu, fft_group_points, fold_lanes=0):
+    t = BatchTuning(BATCH_MODES[mode], fused_chunk, fold_unroll, fold_wg_per_cu, fft_group_points, 0, 0.0, fold_lanes)
     _check(_lib.sfft_batch_set_tuning(batch, ctypes.byref(t)))
 
 
@@ -398,7 +398,7 @@ class Batch:
         t = self.tuning()
         t.update(kw)
         sfft_batch_set_tuning(self.handle, t["mode"], t["fused_chunk"], t["fold_unroll"], t["fold_wg_per_cu"],
-                              t["fft_group_points"])
+                              t["fft_group_points"], t["fold_lanes"])
 
     def set_fold_config(self, unroll, wg_per_cu):
         sfft_batch_set_fold_config(self.handle, unroll, wg_per_cu)

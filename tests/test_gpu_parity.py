@@ -574,7 +574,12 @@ def _check_position_major(sf, dtype, kahan, nsig, ld, location="multiscale", com
     batch = sf.InterleavedBatch(plan, nsig)
     # the three stage launches at two fold shapes give the same bits; the
     # fused persistent launch at two chunk sizes agrees to rounding
+    # signals per fold lane the input allows (the buffers are 256-byte aligned)
+    most = {"c64": 2, "c128": 1, "f16x2": 4}[dtype]
+    lanes = next((L for L in (4, 2) if L <= most and ((nsig + 63) // 64) % L == 0 and nsig % L == 0 and ld % L == 0),
+                 1)
     configs = [dict(mode="stages", fold_unroll=8), dict(mode="stages", fold_unroll=24, fft_group_points=1024),
+               dict(mode="stages", fold_unroll=16, fold_lanes=1),
                dict(mode="fused", fused_chunk=1), dict(mode="fused", fused_chunk=(nsig + 63) // 64)]
     last = {}
     for cfg in configs:
@@ -582,6 +587,8 @@ def _check_position_major(sf, dtype, kahan, nsig, ld, location="multiscale", com
         for _ in range(2):  # a second replay of the same graph
             idx, val, cnt = batch.execute(X, scales=scales)
             torch.cuda.synchronize()
+            if cfg["mode"] == "stages":
+                assert batch.tuning()["fold_lanes"] == cfg.get("fold_lanes", lanes), (cfg, batch.tuning())
             last[cfg["mode"]] = (idx.clone(), val.clone(), cnt.clone())
             for s in range(nsig):
                 c = int(cnt[s].item())
