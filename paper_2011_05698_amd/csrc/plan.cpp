@@ -445,23 +445,29 @@ FoldSplit order_for_stages(std::vector<FoldTile>& tiles) {
 }
 
 // Position-major fold tiles (iteration, block of kIlvItems items, signal
-// group), in an order that keeps a gathered row in the
-// L2 of its XCD for the other rounds that need it: bucket b of round 0
-// and bucket b + (T_j - T_0) mod B of round j gather the same residue class
-// of positions, over windows that overlap when tau_j < w, so the tiles of
-// all rounds for one block of round-0 buckets go out together (and, with
-// signal groups innermost, each group keeps to the same XCD when the number
-// of groups is a multiple of 8).  Every (round, bucket block, group) tile
-// appears once.
+// group), in an order that keeps a gathered row in the L2 of its XCD for the
+// other rounds that need it: bucket b of round 0 and bucket
+// b + (T_j - T_0) mod B of round j gather the same residue class of
+// positions, over windows that overlap when tau_j < w, so the tiles of all
+// rounds for a block of round-0 buckets go out together, signal groups
+// innermost.  Workgroups go to the 8 XCDs in turn, so with 8 groups each
+// group keeps to one XCD.  A fold workgroup that takes two or four adjacent
+// groups (two or four signals per lane) covers fewer XCDs per tile, so runs
+// of kBlockRun blocks interleave round by round: with 8 groups the
+// workgroups of a block and group still meet the same XCD in every round.
+// Every (round, bucket block, group) tile appears once.
 void interleaved_tiles(const HostPlan& hp, uint32_t ngroups, std::vector<FoldTile>& tiles) {
+  constexpr uint32_t kBlockRun = 4;
   for (int m = 0; m < hp.loops; ++m) {
     const IterDesc& d = hp.iters[m].d;
     const uint32_t nb = d.B / kIlvItems;  // B >= 16 = kIlvItems
-    for (uint32_t blk = 0; blk < nb; ++blk)
+    for (uint32_t blk0 = 0; blk0 < nb; blk0 += kBlockRun)
       for (uint32_t j = 0; j <= d.R; ++j) {
         const uint32_t shift = ((d.T[j] - d.T[0]) & (d.B - 1)) / kIlvItems;  // B divides N and 2^32
-        const uint32_t i0 = j * d.B + ((blk + shift) % nb) * kIlvItems;
-        for (uint32_t g = 0; g < ngroups; ++g) tiles.push_back(FoldTile{g, uint32_t(m), i0});
+        for (uint32_t blk = blk0; blk < std::min(blk0 + kBlockRun, nb); ++blk) {
+          const uint32_t i0 = j * d.B + ((blk + shift) % nb) * kIlvItems;
+          for (uint32_t g = 0; g < ngroups; ++g) tiles.push_back(FoldTile{g, uint32_t(m), i0});
+        }
       }
   }
 }
