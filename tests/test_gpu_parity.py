@@ -608,6 +608,8 @@ def _check_position_major(sf, dtype, kahan, nsig, ld, location="multiscale", com
                       1e-10 if dtype == "c128" else 1e-4)
     with pytest.raises(sf.SfftError):
         sf.sfft_execute_interleaved(batch.handle, X, nsig - 1, scales, idx, val, cnt)
+    with pytest.raises(sf.SfftError):  # signals per fold lane: 0 (as allowed), 1, 2 or 4
+        batch.set_tuning(mode="stages", fold_lanes=3)
 
 
 def test_position_major_metric_shape(sf):
