@@ -270,7 +270,12 @@ sfft_status sfft_execute_batch(sfft_batch_t b, const void* const* h_x, const flo
  *            the output value type, d_count device int64 array [nsig].
  * Binding, graph replay and stream ordering are those of sfft_execute_batch
  * (a changed d_x, ld, scale or output pointer re-uploads the descriptor
- * table with a blocking copy).  SFFT_ERR_PARAM for ld < nsig or ld >= 2^32;
+ * table with a blocking copy; a d_x alignment or ld that changes how many
+ * signals a fold lane takes, see fold_lanes, captures the graph again).
+ * The fold reads two (complex64) or four (FP16 pairs) adjacent signals per
+ * load when d_x is aligned to that many elements and ld, nsig and the number
+ * of 64-signal groups are multiples of it; results are the same bits either
+ * way.  SFFT_ERR_PARAM for ld < nsig or ld >= 2^32;
  * SFFT_ERR_STATE when a batch of the other kind is passed to either execute
  * call.  sfft_batch_launch_stage, sfft_batch_set_fold_config (unroll only;
  * wg_per_cu is ignored), sfft_batch_autotune and sfft_batch_destroy apply.
