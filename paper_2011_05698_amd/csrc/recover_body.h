@@ -682,7 +682,7 @@ __device__ void locate_candidates(const PlanDesc* pd, const IterDesc* it, const 
         median_estimate<R>([&](uint32_t j) { return j == 0 ? yi : rows[(j - 1) * ncand + c]; }, it, u, nmask, logN);
     if (g == R(0)) continue;
     cval[c] = cplx<R>{med.re / g, med.im / g};
-    cu[i] = u;
+    cu[c] = u;
   }
 }
 
@@ -786,7 +786,6 @@ __device__ void recover_signal(const SignalDesc& sd, Sh& sh) {
       sv = ar.take<cplx<R>>(nst);
     }
     cplx<R>* y0 = ar.take<cplx<R>>(B);
-    uint32_t* cu = ar.take<uint32_t>(B);  // located position per bucket, or kNone
     R* gw = nullptr;                      // window weight per (entry, reachable bucket), by entry index
     RunBounds* run = nullptr;
     cplx<R>* w0 = nullptr;                // v exp(-2 pi i T_0 u / N) per sorted entry
@@ -821,7 +820,6 @@ __device__ void recover_signal(const SignalDesc& sd, Sh& sh) {
           const uint32_t i = i0 + uint32_t(e) * NT + tid;
           if (i < B) {
             y0[i] = y[e];
-            cu[i] = kNone;
             if (!subtract) pk[i] = RK::bits(y[e].re * y[e].re + y[e].im * y[e].im);
           }
           if (i < nst) {
@@ -1057,18 +1055,23 @@ __device__ void recover_signal(const SignalDesc& sd, Sh& sh) {
     // ---- 6. the round-to-round test, then phase differences ----
     // ---- 7. location, verification, median estimation ----
     cplx<R>* cval;  // estimates of the located candidates
+    uint32_t* cu;   // located position per candidate, or kNone
     consistency<R, Sh::kThreads>(y0, cand, rows, ncand, R_, R(pd->rho), good, &sh.ngood);
     __syncthreads();
     const uint32_t ngood = sh.ngood;
     if (ang32) {
       uint32_t* th = ar.take<uint32_t>(nitems);
       cval = ar.take<cplx<R>>(ncand);
+      cu = ar.take<uint32_t>(ncand);
+      for (uint32_t c = tid; c < ncand; c += NT) cu[c] = kNone;
       angles<uint32_t, R, Sh::kThreads>(y0, cand, rows, ncand, R_, fp64, good, ngood, th);
       __syncthreads();
       locate_candidates<uint32_t, R, Sh::kThreads>(pd, it, ghat, y0, cand, rows, th, good, ngood, ncand, cu, cval);
     } else {
       uint64_t* th = ar.take<uint64_t>(nitems);
       cval = ar.take<cplx<R>>(ncand);
+      cu = ar.take<uint32_t>(ncand);
+      for (uint32_t c = tid; c < ncand; c += NT) cu[c] = kNone;
       angles<uint64_t, R, Sh::kThreads>(y0, cand, rows, ncand, R_, fp64, good, ngood, th);
       __syncthreads();
       locate_candidates<uint64_t, R, Sh::kThreads>(pd, it, ghat, y0, cand, rows, th, good, ngood, ncand, cu, cval);
@@ -1079,8 +1082,7 @@ __device__ void recover_signal(const SignalDesc& sd, Sh& sh) {
     // Verification keeps a position only in its home bucket, so each located
     // position is one candidate.
     for (uint32_t c = tid; c < ncand; c += NT) {
-      const uint32_t i = cand[c];
-      const uint32_t u = cu[i];
+      const uint32_t u = cu[c];
       if (u == kNone) continue;
       const uint32_t f = (it->sigma_inv * u) & nmask;
       const cplx<R> v = cval[c];
